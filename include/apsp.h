@@ -1,0 +1,187 @@
+/*
+ * apsp.h -- C ABI of the MI355X min-plus all-pairs-shortest-paths library.
+ *
+ * Method: T. Anjary, "The Floyd-Warshall Algorithm Re-implemented Using
+ * 3D-Tensors and Hardware Acceleration", arXiv 2310.03983.
+ *
+ * Problem statement (Sec. 2 and Sec. 3.1):
+ *   A graph on n vertices is given as a dense n x n cost matrix D, row-major
+ *   with leading dimension ldd >= n elements; D[i*ldd + j] is the cost of the
+ *   edge i -> j (row = "from" vertex, column = "to" vertex).  D[i][i] = 0
+ *   (Sec. 3.4) and a missing edge holds INF.  Costs are non-negative.
+ *   The solvers overwrite D in place with shortest-path distances.
+ *
+ * Element types (apsp_dtype_t):
+ *   APSP_I32  int32 costs in [0, APSP_INF_I32]; APSP_INF_I32 = 2^30 means
+ *             "no path".  Addition saturates: a (+) b = min(a + b, INF), so
+ *             every result is exactly min(true distance, INF).
+ *   APSP_F32  IEEE binary32 costs >= 0, +inf means "no path".  Each min-plus
+ *             term is one round-to-nearest-even addition.
+ *
+ * Memory and streams: every matrix, offset and size array passed to a compute
+ * call is device memory owned by the caller; the library keeps no pointer
+ * past the call.  `stream` is a hipStream_t (NULL = the legacy default
+ * stream).  Compute calls only enqueue work and return; a device fault is
+ * reported by the caller's next synchronisation.  Value preconditions
+ * (diagonal 0, range) are not checked by compute calls; apsp_validate checks
+ * them.
+ *
+ * Errors: every call returns an apsp_status_t.  Argument errors are detected
+ * before anything is enqueued.  apsp_last_error() returns a thread-local
+ * message describing the last failure on the calling thread.
+ */
+#ifndef APSP_H
+#define APSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t apsp_status_t;
+#define APSP_OK             0
+#define APSP_E_ARG         -1   /* null pointer, negative size, ld too small, bad dtype/option */
+#define APSP_E_INPUT       -2   /* apsp_validate found a precondition violation */
+#define APSP_E_NOMEM       -3   /* device allocation for library scratch failed */
+#define APSP_E_HIP         -4   /* a HIP runtime call or kernel launch failed */
+#define APSP_E_UNSUPPORTED -5   /* option not available for this dtype/size */
+#define APSP_E_STATE       -6   /* context not usable (wrong device, destroyed) */
+
+typedef int32_t apsp_dtype_t;
+#define APSP_I32 0
+#define APSP_F32 1
+
+#define APSP_INF_I32 1073741824  /* 2^30 */
+
+/* Algorithm choice (apsp_opts_t.algo). */
+#define APSP_ALGO_AUTO     0   /* planner decides */
+#define APSP_ALGO_FW       1   /* three-phase blocked Floyd-Warshall (Sec. 2, Eq. 1) */
+#define APSP_ALGO_RKLEENE  2   /* R-Kleene quadrant recursion (Sec. 3.3, Eq. 4) */
+#define APSP_ALGO_SQUARE   3   /* min-plus squaring to a fixpoint (Sec. 3.2) */
+
+/* Closure of a diagonal tile (apsp_opts_t.closure). */
+#define APSP_CLOSURE_AUTO   0
+#define APSP_CLOSURE_KLOOP  1  /* Eq. 1 k-loop held in LDS */
+#define APSP_CLOSURE_SQUARE 2  /* X <- min(X, X (min,+) X) until unchanged (Sec. 3.2) */
+
+/* GEMM macro-tile (apsp_opts_t.tile). */
+#define APSP_TILE_AUTO    0
+#define APSP_TILE_128     1   /* 128 x 128 output tile per workgroup */
+#define APSP_TILE_64      2   /* 64 x 64 output tile per workgroup */
+
+/* Flags (apsp_opts_t.flags). */
+#define APSP_FLAG_NO_SPLITK  1  /* never split the reduction dimension */
+
+typedef struct apsp_opts {
+    int32_t algo;      /* APSP_ALGO_*; only apsp_solve and apsp_batched read it */
+    int32_t block;     /* FW round width / R-Kleene leaf size: 0 (auto), 64 or 128 */
+    int32_t tile;      /* APSP_TILE_* for the min-plus products */
+    int32_t closure;   /* APSP_CLOSURE_* for diagonal tiles */
+    int32_t cutover;   /* R-Kleene: sub-problems <= cutover use blocked FW (0 = never) */
+    int32_t flags;     /* APSP_FLAG_* bits */
+    int32_t reserved[6];
+} apsp_opts_t;
+
+typedef struct apsp_ctx apsp_ctx_t;
+
+/* Creates a context bound to HIP device `device` and allocates its small
+ * device scratch (counters, batched plan table).  *ctx receives the handle. */
+apsp_status_t apsp_create(apsp_ctx_t **ctx, int32_t device);
+
+/* Synchronises the device, frees the scratch and the handle.  NULL is a no-op. */
+apsp_status_t apsp_destroy(apsp_ctx_t *ctx);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char *apsp_last_error(void);
+
+/* Library version string. */
+const char *apsp_version(void);
+
+/*
+ * Min-plus product, accumulating form (Sec. 3, Eq. 2):
+ *     C[i][j] <- min(C[i][j], min_{0<=t<k} A[i][t] (+) B[t][j])
+ * A is m x k (lda >= k), B is k x n (ldb >= n), C is m x n (ldc >= n), all
+ * row-major device arrays of `dtype`.  Filling C with INF first gives Eq. 2
+ * exactly.  k = 0, m = 0 or n = 0 leaves C unchanged.  The result is exact
+ * and unique in both dtypes (min is exact and each term is rounded once).
+ * C must not overlap A or B (APSP_E_ARG).  Preconditions: A, B, C in
+ * [0, INF] (int32) / >= 0 (fp32).
+ */
+apsp_status_t minplus_gemm(apsp_ctx_t *ctx, apsp_dtype_t dtype,
+                           int64_t m, int64_t n, int64_t k,
+                           const void *A, int64_t lda,
+                           const void *B, int64_t ldb,
+                           void *C, int64_t ldc,
+                           const apsp_opts_t *opts, void *stream);
+
+/*
+ * Closure of one square block of at most 128 x 128 (Sec. 2, Eq. 1 applied to
+ * the block alone): D <- D*, i.e. shortest paths that stay inside the block.
+ * opts->closure picks the Eq. 1 k-loop or squaring to a fixpoint (Sec. 3.2).
+ * n in [0, 128]; otherwise APSP_E_UNSUPPORTED.
+ */
+apsp_status_t apsp_closure(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                           void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/*
+ * All-pairs shortest paths by three-phase blocked Floyd-Warshall (Sec. 2,
+ * Eq. 1): for each round of width b, close the diagonal tile, update its row
+ * and column panels, then every remaining tile with one min-plus product.
+ * D (n x n, ldd >= n) is overwritten with distances.  opts may be NULL.
+ */
+apsp_status_t apsp_fw(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                      void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/*
+ * All-pairs shortest paths by the R-Kleene recursion (Sec. 3.3, Eq. 4): split
+ * D into [[A, B], [C, D]], close A, update B, C and D through A, close D,
+ * update B and C through D and finally A.  Sub-blocks are strided views of
+ * the one buffer; products whose output is also an operand run in place
+ * (every stored value stays the length of a real walk, so the int32 result
+ * is exact; fp32 results stay within rounding of the exact distances).
+ */
+apsp_status_t apsp_rkleene(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                           void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/*
+ * All-pairs shortest paths by repeated min-plus squaring (Sec. 3.2):
+ * D <- min(D, D (min,+) D) until no entry changes (at most
+ * ceil(log2(n-1)) + 1 passes).  Uses a 4-byte device flag in the context
+ * scratch and synchronises `stream` once per pass to read it.
+ */
+apsp_status_t apsp_square(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                          void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/* Dispatches to apsp_fw / apsp_rkleene / apsp_square per opts->algo; with
+ * APSP_ALGO_AUTO (or opts == NULL) the planner (apsp_plan) decides. */
+apsp_status_t apsp_solve(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                         void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/*
+ * Many independent graphs in one launch.  `data` holds `count` square
+ * row-major matrices back to back; d_offsets[g] (int64, device) is the
+ * element offset of graph g and d_sizes[g] (int32, device) its n; h_sizes is
+ * the same sizes on the host (used to plan, never dereferenced on device).
+ * Every matrix is overwritten with its distances.  n <= 512 per graph;
+ * larger graphs give APSP_E_UNSUPPORTED (use apsp_solve).
+ */
+apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
+                           void *data, const int64_t *d_offsets, const int32_t *d_sizes,
+                           const int32_t *h_sizes, const apsp_opts_t *opts, void *stream);
+
+/*
+ * Checks the input contract of an n x n matrix (Sec. 3.1 and 3.4): diagonal
+ * exactly 0; int32 entries in [0, INF]; fp32 entries >= 0 and not NaN.
+ * Synchronous: waits for `stream`, writes the number of violating entries to
+ * *h_violations and returns APSP_E_INPUT if it is non-zero.
+ */
+apsp_status_t apsp_validate(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                            const void *D, int64_t ldd, void *stream, int64_t *h_violations);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APSP_H */

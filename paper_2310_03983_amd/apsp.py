@@ -1,0 +1,225 @@
+"""Python binding of libapsp (include/apsp.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and forwards
+device pointers, leading dimensions and torch's current HIP stream; all
+arithmetic happens in the HIP kernels behind the C ABI.  torch is used only
+for device memory and streams.  If libapsp.so has not been built the import
+fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libapsp.so")
+
+APSP_OK, APSP_E_ARG, APSP_E_INPUT, APSP_E_NOMEM, APSP_E_HIP, APSP_E_UNSUPPORTED, APSP_E_STATE = 0, -1, -2, -3, -4, -5, -6
+APSP_I32, APSP_F32 = 0, 1
+INF_I32 = 1 << 30
+ALGO = {"auto": 0, "fw": 1, "rkleene": 2, "square": 3}
+CLOSURE = {"auto": 0, "kloop": 1, "square": 2}
+TILE = {"auto": 0, 128: 1, 64: 2}
+FLAG_NO_SPLITK = 1
+
+# every symbol include/apsp.h declares
+EXPORTS = [
+    "apsp_create", "apsp_destroy", "apsp_last_error", "apsp_version",
+    "minplus_gemm", "apsp_closure", "apsp_fw", "apsp_rkleene", "apsp_square",
+    "apsp_solve", "apsp_batched", "apsp_validate",
+]
+
+
+class ApspError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+        self.message = message
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("block", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("closure", ctypes.c_int32), ("cutover", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True) -> Opts:
+    o = Opts()
+    o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
+    o.block = int(block)
+    o.tile = TILE[tile]
+    o.closure = CLOSURE[closure] if isinstance(closure, str) else int(closure)
+    o.cutover = int(cutover)
+    o.flags = 0 if splitk else FLAG_NO_SPLITK
+    return o
+
+
+_lock = threading.Lock()
+_lib = None
+_ctxs: dict[int, ctypes.c_void_p] = {}
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libapsp.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -m paper_2310_03983_amd.build` (there is no CPU fallback)")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+            P = ctypes.POINTER
+            L.apsp_create.argtypes = [P(vp), i32]
+            L.apsp_destroy.argtypes = [vp]
+            L.apsp_last_error.restype = ctypes.c_char_p
+            L.apsp_last_error.argtypes = []
+            L.apsp_version.restype = ctypes.c_char_p
+            L.apsp_version.argtypes = []
+            L.minplus_gemm.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, P(Opts), vp]
+            for name in ("apsp_closure", "apsp_fw", "apsp_rkleene", "apsp_square", "apsp_solve"):
+                getattr(L, name).argtypes = [vp, i32, i64, vp, i64, P(Opts), vp]
+            L.apsp_batched.argtypes = [vp, i32, i32, vp, vp, vp, P(i32), P(Opts), vp]
+            L.apsp_validate.argtypes = [vp, i32, i64, vp, i64, vp, P(i64)]
+            for name in EXPORTS:
+                if name not in ("apsp_last_error", "apsp_version"):
+                    getattr(L, name).restype = i32
+            _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().apsp_last_error().decode()
+
+
+def _check(status: int):
+    if status != APSP_OK:
+        raise ApspError(status, last_error())
+
+
+def context(device: int | None = None) -> ctypes.c_void_p:
+    """The library context of a HIP device (created once per process)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    with _lock:
+        c = _ctxs.get(device)
+    if c is None:
+        c = ctypes.c_void_p()
+        _check(lib().apsp_create(ctypes.byref(c), device))
+        with _lock:
+            _ctxs[device] = c
+    return c
+
+
+def _dtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.int32:
+        return APSP_I32
+    if t.dtype == torch.float32:
+        return APSP_F32
+    raise TypeError(f"dtype {t.dtype} is not supported (int32 or float32)")
+
+
+def _matrix(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit column stride")
+    return t.data_ptr(), max(t.stride(0), t.shape[1])
+
+
+def _stream(t: torch.Tensor, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _opts(opts, kw) -> Opts:
+    if opts is not None:
+        return opts
+    return make_opts(**kw)
+
+
+def minplus_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, opts: Opts | None = None,
+                 stream=None, **kw) -> torch.Tensor:
+    """C <- min(C, A (min,+) B) in place (Sec. 3, Eq. 2); returns C."""
+    dt = _dtype(C)
+    if A.dtype != C.dtype or B.dtype != C.dtype:
+        raise TypeError("A, B and C must share a dtype")
+    pa, lda = _matrix(A, "A")
+    pb, ldb = _matrix(B, "B")
+    pc, ldc = _matrix(C, "C")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    o = _opts(opts, kw)
+    _check(lib().minplus_gemm(context(C.device.index), dt, m, n, k, pa, lda, pb, ldb, pc, ldc,
+                              ctypes.byref(o), _stream(C, stream)))
+    return C
+
+
+def _square_call(name, D, opts, stream, kw):
+    dt = _dtype(D)
+    p, ld = _matrix(D, "D")
+    n = D.shape[0]
+    if D.shape[1] != n:
+        raise ValueError("D must be square")
+    o = _opts(opts, kw)
+    _check(getattr(lib(), name)(context(D.device.index), dt, n, p, ld, ctypes.byref(o), _stream(D, stream)))
+    return D
+
+
+def apsp_closure(D, opts=None, stream=None, **kw):
+    """Closure of one block of at most 128 x 128 (Sec. 2, Eq. 1); in place."""
+    return _square_call("apsp_closure", D, opts, stream, kw)
+
+
+def apsp_fw(D, opts=None, stream=None, **kw):
+    """Three-phase blocked Floyd-Warshall (Sec. 2, Eq. 1); D is overwritten."""
+    return _square_call("apsp_fw", D, opts, stream, kw)
+
+
+def apsp_rkleene(D, opts=None, stream=None, **kw):
+    """R-Kleene quadrant recursion (Sec. 3.3, Eq. 4); D is overwritten."""
+    return _square_call("apsp_rkleene", D, opts, stream, kw)
+
+
+def apsp_square(D, opts=None, stream=None, **kw):
+    """Min-plus squaring until unchanged (Sec. 3.2); D is overwritten."""
+    return _square_call("apsp_square", D, opts, stream, kw)
+
+
+def apsp_solve(D, opts=None, stream=None, **kw):
+    """Planner-selected algorithm; D is overwritten."""
+    return _square_call("apsp_solve", D, opts, stream, kw)
+
+
+def apsp_validate(D, stream=None) -> int:
+    """Number of entries violating the input contract (synchronous)."""
+    dt = _dtype(D)
+    p, ld = _matrix(D, "D")
+    n = D.shape[0]
+    v = ctypes.c_int64(0)
+    st = lib().apsp_validate(context(D.device.index), dt, n, p, ld, _stream(D, stream), ctypes.byref(v))
+    if st not in (APSP_OK, APSP_E_INPUT):
+        _check(st)
+    return int(v.value)
+
+
+def apsp_batched(data: torch.Tensor, offsets: torch.Tensor, sizes: torch.Tensor, h_sizes,
+                 opts=None, stream=None, **kw):
+    """Closes every graph of a ragged batch in one launch; `data` is overwritten."""
+    dt = _dtype(data)
+    if not (data.is_cuda and offsets.is_cuda and sizes.is_cuda):
+        raise TypeError("data, offsets and sizes must be device tensors")
+    if offsets.dtype != torch.int64 or sizes.dtype != torch.int32:
+        raise TypeError("offsets must be int64 and sizes int32")
+    count = len(h_sizes)
+    hs = (ctypes.c_int32 * max(count, 1))(*[int(x) for x in h_sizes])
+    o = _opts(opts, kw)
+    _check(lib().apsp_batched(context(data.device.index), dt, count, data.data_ptr(), offsets.data_ptr(),
+                              sizes.data_ptr(), hs, ctypes.byref(o), _stream(data, stream)))
+    return data

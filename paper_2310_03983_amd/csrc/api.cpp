@@ -1,0 +1,473 @@
+// C ABI of libapsp (include/apsp.h) and the host drivers that sequence the
+// kernels: the blocked Floyd-Warshall round loop, the R-Kleene recursion and
+// min-plus squaring.  Every driver only enqueues work on the caller's
+// stream; argument checks run before the first HIP call.
+#include "apsp.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+struct apsp_ctx {
+    int device = 0;
+    int num_cus = 256;
+    void* d_scratch = nullptr;      // counters and flags
+    size_t scratch_bytes = 0;
+    void* d_plan = nullptr;         // batched plan table (grown on demand)
+    size_t plan_bytes = 0;
+    uint32_t magic = 0x41505350;    // "APSP"
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+apsp_status_t fail(apsp_status_t st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+apsp_status_t hip_fail(hipError_t e, const char* where)
+{
+    return fail(APSP_E_HIP, "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(expr, where)                         \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+// Forced failure for host-side error-path tests: APSP_FAULT=launch makes the
+// first kernel enqueue of a call report a HIP error without touching a GPU.
+bool fault_injected(const char* what)
+{
+    const char* f = getenv("APSP_FAULT");
+    return f && strcmp(f, what) == 0;
+}
+
+apsp_status_t check_ctx(apsp_ctx_t* ctx)
+{
+    if (!ctx) return fail(APSP_E_ARG, "context is NULL");
+    if (ctx->magic != 0x41505350) return fail(APSP_E_STATE, "context is not valid (destroyed?)");
+    return APSP_OK;
+}
+
+apsp_status_t check_dtype(apsp_dtype_t dt)
+{
+    if (dt != APSP_I32 && dt != APSP_F32) return fail(APSP_E_ARG, "unknown dtype %d", (int)dt);
+    return APSP_OK;
+}
+
+apsp_status_t check_square(int64_t n, const void* D, int64_t ld)
+{
+    if (n < 0) return fail(APSP_E_ARG, "n = %lld is negative", (long long)n);
+    if (n > (int64_t)1 << 30) return fail(APSP_E_ARG, "n = %lld is too large", (long long)n);
+    if (n > 0 && !D) return fail(APSP_E_ARG, "matrix pointer is NULL");
+    if (n > 0 && ld < n) return fail(APSP_E_ARG, "ld = %lld < n = %lld", (long long)ld, (long long)n);
+    return APSP_OK;
+}
+
+const apsp_opts_t* opts_or_default(const apsp_opts_t* o)
+{
+    static const apsp_opts_t zero{};
+    return o ? o : &zero;
+}
+
+apsp_status_t check_opts(const apsp_opts_t* o)
+{
+    if (o->block != 0 && o->block != 64 && o->block != 128)
+        return fail(APSP_E_ARG, "block = %d (allowed: 0, 64, 128)", o->block);
+    if (o->tile < 0 || o->tile > APSP_TILE_64) return fail(APSP_E_ARG, "tile = %d", o->tile);
+    if (o->closure < 0 || o->closure > APSP_CLOSURE_SQUARE) return fail(APSP_E_ARG, "closure = %d", o->closure);
+    if (o->algo < 0 || o->algo > APSP_ALGO_SQUARE) return fail(APSP_E_ARG, "algo = %d", o->algo);
+    if (o->cutover < 0) return fail(APSP_E_ARG, "cutover = %d", o->cutover);
+    return APSP_OK;
+}
+
+size_t esize(apsp_dtype_t) { return 4; }
+
+char* elem(void* base, apsp_dtype_t dt, int64_t r, int64_t c, int64_t ld)
+{
+    return static_cast<char*>(base) + (r * ld + c) * (int64_t)esize(dt);
+}
+
+struct Plan {
+    int block;      // FW round width / R-Kleene leaf size
+    int tile;       // GEMM tile for big products
+    int closure;    // 1 k-loop, 2 squaring
+    int cutover;    // R-Kleene -> FW below this size
+    bool splitk;
+};
+
+Plan resolve(const apsp_opts_t* o)
+{
+    Plan p;
+    p.block = o->block ? o->block : 128;
+    p.tile = o->tile ? o->tile : apsp::TILE_128;
+    p.closure = o->closure ? o->closure : APSP_CLOSURE_KLOOP;
+    p.cutover = o->cutover;
+    p.splitk = !(o->flags & APSP_FLAG_NO_SPLITK);
+    return p;
+}
+
+apsp::GemmProblem make_problem(apsp_dtype_t dt, void* base, int64_t ld,
+                               int64_t ar, int64_t ac,      // A origin
+                               int64_t br, int64_t bc,      // B origin
+                               int64_t cr, int64_t cc,      // C origin
+                               int64_t M, int64_t N, int64_t K)
+{
+    apsp::GemmProblem p{};
+    p.A = elem(base, dt, ar, ac, ld);
+    p.B = elem(base, dt, br, bc, ld);
+    p.C = elem(base, dt, cr, cc, ld);
+    p.lda = p.ldb = p.ldc = ld;
+    p.M = (int32_t)M;
+    p.N = (int32_t)N;
+    p.K = (int32_t)K;
+    return p;
+}
+
+// Tile for a product: small outputs use 64 x 64 tiles to fill the device.
+int pick_tile(const Plan& pl, int64_t M, int64_t N)
+{
+    if (pl.tile == apsp::TILE_64) return apsp::TILE_64;
+    const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
+    if (t128 < 512) return apsp::TILE_64;
+    return apsp::TILE_128;
+}
+
+apsp_status_t run_group(apsp_ctx_t* ctx, apsp_dtype_t dt, apsp::GemmGroup& g, const Plan& pl,
+                        int tile, hipStream_t st)
+{
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    apsp::finalize_group(g, tile, pl.splitk ? 2 * ctx->num_cus : 0);
+    HIP_TRY(apsp::launch_minplus((apsp::DType)dt, tile, g, st), "min-plus launch");
+    return APSP_OK;
+}
+
+apsp_status_t run_one(apsp_ctx_t* ctx, apsp_dtype_t dt, const apsp::GemmProblem& p, const Plan& pl,
+                      hipStream_t st)
+{
+    if (p.M <= 0 || p.N <= 0 || p.K <= 0) return APSP_OK;
+    apsp::GemmGroup g{};
+    g.count = 1;
+    g.p[0] = p;
+    return run_group(ctx, dt, g, pl, pick_tile(pl, p.M, p.N), st);
+}
+
+apsp_status_t run_two(apsp_ctx_t* ctx, apsp_dtype_t dt, const apsp::GemmProblem& p,
+                      const apsp::GemmProblem& q, const Plan& pl, hipStream_t st)
+{
+    apsp::GemmGroup g{};
+    const int64_t mm = std::max<int64_t>(p.M, q.M), nn = std::max<int64_t>(p.N, q.N);
+    if (p.M > 0 && p.N > 0 && p.K > 0) g.p[g.count++] = p;
+    if (q.M > 0 && q.N > 0 && q.K > 0) g.p[g.count++] = q;
+    if (!g.count) return APSP_OK;
+    return run_group(ctx, dt, g, pl, pick_tile(pl, mm, nn), st);
+}
+
+apsp_status_t closure(apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t s, int kind,
+                      hipStream_t st)
+{
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    HIP_TRY(apsp::launch_closure((apsp::DType)dt, kind, elem(D, dt, off, off, ld), ld, (int32_t)s, st),
+            "closure launch");
+    return APSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Floyd-Warshall on the window [off, off+n) x [off, off+n)
+// ---------------------------------------------------------------------------
+apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
+                        const Plan& pl, hipStream_t st)
+{
+    const int64_t b = pl.block;
+    const int t_p2 = apsp::TILE_64;                 // panels are thin: small tiles
+    // the excluded pivot band must be whole tiles: 64-wide rounds use 64-tiles
+    const int t_p3 = (b < 128) ? (int)apsp::TILE_64 : pick_tile(pl, n, n);
+    const apsp::TileShape s2 = apsp::tile_shape(t_p2), s3 = apsp::tile_shape(t_p3);
+    for (int64_t k0 = 0; k0 < n; k0 += b) {
+        const int64_t bk = std::min(b, n - k0);
+        // phase 1: close the pivot tile
+        apsp_status_t rc = closure(dt, D, ld, off + k0, bk, pl.closure, st);
+        if (rc) return rc;
+        if (bk == n) break;
+        // phase 2: row panel R_KJ <- X* (min,+) R_KJ and column panel C_IK <- C_IK (min,+) X*
+        apsp::GemmGroup g2{};
+        g2.count = 2;
+        g2.p[0] = make_problem(dt, D, ld, off + k0, off + k0, off + k0, off, off + k0, off, bk, n, bk);
+        g2.p[0].skip_n0 = (int32_t)(k0 / s2.nt);
+        g2.p[0].skip_nc = (int32_t)((bk + s2.nt - 1) / s2.nt);
+        g2.p[1] = make_problem(dt, D, ld, off, off + k0, off + k0, off + k0, off, off + k0, n, bk, bk);
+        g2.p[1].skip_m0 = (int32_t)(k0 / s2.mt);
+        g2.p[1].skip_mc = (int32_t)((bk + s2.mt - 1) / s2.mt);
+        rc = run_group(ctx, dt, g2, pl, t_p2, st);
+        if (rc) return rc;
+        // phase 3: D_IJ <- min(D_IJ, C_IK (min,+) R_KJ) for I, J outside the pivot band
+        apsp::GemmGroup g3{};
+        g3.count = 1;
+        g3.p[0] = make_problem(dt, D, ld, off, off + k0, off + k0, off, off, off, n, n, bk);
+        g3.p[0].skip_m0 = (int32_t)(k0 / s3.mt);
+        g3.p[0].skip_mc = (int32_t)((bk + s3.mt - 1) / s3.mt);
+        g3.p[0].skip_n0 = (int32_t)(k0 / s3.nt);
+        g3.p[0].skip_nc = (int32_t)((bk + s3.nt - 1) / s3.nt);
+        rc = run_group(ctx, dt, g3, pl, t_p3, st);
+        if (rc) return rc;
+    }
+    return APSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// R-Kleene on the window [off, off+n)^2 (Sec. 3.3, Eq. 4)
+// ---------------------------------------------------------------------------
+apsp_status_t rk_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
+                        const Plan& pl, hipStream_t st)
+{
+    if (n <= pl.block) return closure(dt, D, ld, off, n, pl.closure, st);
+    if (pl.cutover > 0 && n <= pl.cutover) return fw_window(ctx, dt, D, ld, off, n, pl, st);
+    // split point: half, rounded up to a multiple of the leaf size (so every
+    // leaf and every sub-view starts on a tile boundary)
+    int64_t n1 = (n + 1) / 2;
+    n1 = (n1 + pl.block - 1) / pl.block * pl.block;
+    if (n1 >= n) n1 = n - 1;
+    const int64_t n2 = n - n1;
+    const int64_t a = off, d = off + n1;
+    apsp_status_t rc;
+    // A <- A*
+    if ((rc = rk_window(ctx, dt, D, ld, a, n1, pl, st))) return rc;
+    // B <- min(B, A (min,+) B);  C <- min(C, C (min,+) A)
+    rc = run_two(ctx, dt,
+                 make_problem(dt, D, ld, a, a, a, d, a, d, n1, n2, n1),
+                 make_problem(dt, D, ld, d, a, a, a, d, a, n2, n1, n1), pl, st);
+    if (rc) return rc;
+    // D <- min(D, C (min,+) B)
+    if ((rc = run_one(ctx, dt, make_problem(dt, D, ld, d, a, a, d, d, d, n2, n2, n1), pl, st))) return rc;
+    // D <- D*
+    if ((rc = rk_window(ctx, dt, D, ld, d, n2, pl, st))) return rc;
+    // B <- min(B, B (min,+) D);  C <- min(C, D (min,+) C)
+    rc = run_two(ctx, dt,
+                 make_problem(dt, D, ld, a, d, d, d, a, d, n1, n2, n2),
+                 make_problem(dt, D, ld, d, d, d, a, d, a, n2, n1, n2), pl, st);
+    if (rc) return rc;
+    // A <- min(A, B (min,+) C)
+    return run_one(ctx, dt, make_problem(dt, D, ld, a, d, d, a, a, a, n1, n1, n2), pl, st);
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + bbytes && y < x + abytes;
+}
+
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld)
+{
+    if (rows <= 0 || cols <= 0) return 0;
+    return (size_t)(((rows - 1) * ld + cols) * 4);
+}
+
+apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ld,
+                            const Plan& pl, hipStream_t st)
+{
+    if (n <= 1) return APSP_OK;
+    uint32_t* flag = static_cast<uint32_t*>(ctx->d_scratch) + 4;
+    int passes = 0;
+    for (;;) {
+        if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+        HIP_TRY(apsp::launch_fill_u32(flag, 0u, 1, st), "flag reset");
+        HIP_TRY(apsp::launch_square_pass((apsp::DType)dt, pick_tile(pl, n, n), D, n, ld, flag, st),
+                "squaring pass");
+        uint32_t h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st), "flag copy");
+        HIP_TRY(hipStreamSynchronize(st), "flag sync");
+        ++passes;
+        if (!h) break;
+        if (passes > 64) return fail(APSP_E_INPUT, "squaring did not converge (negative costs?)");
+    }
+    return APSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* apsp_last_error(void) { return g_last_error.c_str(); }
+
+const char* apsp_version(void) { return "apsp-mi355x 0.1 (gfx950)"; }
+
+apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
+{
+    if (!out) return fail(APSP_E_ARG, "ctx output pointer is NULL");
+    *out = nullptr;
+    if (device < 0) return fail(APSP_E_ARG, "device = %d", device);
+    if (fault_injected("create")) return fail(APSP_E_HIP, "injected create failure");
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
+    if (device >= count) return fail(APSP_E_ARG, "device %d of %d", device, count);
+    HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    apsp_ctx_t* c = new apsp_ctx_t();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
+    c->scratch_bytes = 4096;
+    hipError_t e = hipMalloc(&c->d_scratch, c->scratch_bytes);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(APSP_E_NOMEM, "scratch allocation: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return APSP_OK;
+}
+
+apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
+{
+    if (!ctx) return APSP_OK;
+    if (ctx->magic != 0x41505350) return fail(APSP_E_STATE, "context is not valid");
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    if (ctx->d_scratch) hipFree(ctx->d_scratch);
+    if (ctx->d_plan) hipFree(ctx->d_plan);
+    ctx->magic = 0;
+    delete ctx;
+    return APSP_OK;
+}
+
+apsp_status_t minplus_gemm(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t m, int64_t n, int64_t k,
+                           const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc,
+                           const apsp_opts_t* opts, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt))) return rc;
+    const apsp_opts_t* o = opts_or_default(opts);
+    if ((rc = check_opts(o))) return rc;
+    if (m < 0 || n < 0 || k < 0) return fail(APSP_E_ARG, "negative size m=%lld n=%lld k=%lld",
+                                             (long long)m, (long long)n, (long long)k);
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2) return fail(APSP_E_ARG, "size too large");
+    if (m == 0 || n == 0 || k == 0) return check_ctx(ctx);
+    if (!A || !B || !C) return fail(APSP_E_ARG, "NULL matrix pointer");
+    if (lda < k) return fail(APSP_E_ARG, "lda = %lld < k = %lld", (long long)lda, (long long)k);
+    if (ldb < n) return fail(APSP_E_ARG, "ldb = %lld < n = %lld", (long long)ldb, (long long)n);
+    if (ldc < n) return fail(APSP_E_ARG, "ldc = %lld < n = %lld", (long long)ldc, (long long)n);
+    const size_t cb = span_bytes(m, n, ldc);
+    if (overlaps(C, cb, A, span_bytes(m, k, lda)) || overlaps(C, cb, B, span_bytes(k, n, ldb)))
+        return fail(APSP_E_ARG, "C overlaps A or B");
+    if ((rc = check_ctx(ctx))) return rc;
+    const Plan pl = resolve(o);
+    apsp::GemmProblem p{};
+    p.A = A; p.B = B; p.C = C;
+    p.lda = lda; p.ldb = ldb; p.ldc = ldc;
+    p.M = (int32_t)m; p.N = (int32_t)n; p.K = (int32_t)k;
+    return run_one(ctx, dt, p, pl, static_cast<hipStream_t>(stream));
+}
+
+apsp_status_t apsp_closure(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
+                           const apsp_opts_t* opts, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
+    const apsp_opts_t* o = opts_or_default(opts);
+    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    if (n > 128) return fail(APSP_E_UNSUPPORTED, "closure block n = %lld > 128", (long long)n);
+    if (n <= 1) return APSP_OK;
+    const Plan pl = resolve(o);
+    return closure(dt, D, ldd, 0, n, pl.closure, static_cast<hipStream_t>(stream));
+}
+
+apsp_status_t apsp_fw(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
+                      const apsp_opts_t* opts, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
+    const apsp_opts_t* o = opts_or_default(opts);
+    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    if (n <= 1) return APSP_OK;
+    const Plan pl = resolve(o);
+    return fw_window(ctx, dt, D, ldd, 0, n, pl, static_cast<hipStream_t>(stream));
+}
+
+apsp_status_t apsp_rkleene(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
+                           const apsp_opts_t* opts, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
+    const apsp_opts_t* o = opts_or_default(opts);
+    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    if (n <= 1) return APSP_OK;
+    const Plan pl = resolve(o);
+    return rk_window(ctx, dt, D, ldd, 0, n, pl, static_cast<hipStream_t>(stream));
+}
+
+apsp_status_t apsp_square(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
+                          const apsp_opts_t* opts, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
+    const apsp_opts_t* o = opts_or_default(opts);
+    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    const Plan pl = resolve(o);
+    return square_common(ctx, dt, n, D, ldd, pl, static_cast<hipStream_t>(stream));
+}
+
+apsp_status_t apsp_solve(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
+                         const apsp_opts_t* opts, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
+    const apsp_opts_t* o = opts_or_default(opts);
+    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    switch (o->algo) {
+    case APSP_ALGO_FW: return apsp_fw(ctx, dt, n, D, ldd, o, stream);
+    case APSP_ALGO_SQUARE: return apsp_square(ctx, dt, n, D, ldd, o, stream);
+    case APSP_ALGO_RKLEENE: return apsp_rkleene(ctx, dt, n, D, ldd, o, stream);
+    default:
+        // R-Kleene's top-level products are large and efficient; blocked FW
+        // has fewer launches on small graphs
+        if (n <= 1024) return apsp_fw(ctx, dt, n, D, ldd, o, stream);
+        return apsp_rkleene(ctx, dt, n, D, ldd, o, stream);
+    }
+}
+
+apsp_status_t apsp_validate(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
+                            void* stream, int64_t* h_violations)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
+    if (!h_violations) return fail(APSP_E_ARG, "h_violations is NULL");
+    if ((rc = check_ctx(ctx))) return rc;
+    *h_violations = 0;
+    if (n == 0) return APSP_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    unsigned long long* cnt = static_cast<unsigned long long*>(ctx->d_scratch);
+    HIP_TRY(apsp::launch_validate((apsp::DType)dt, D, n, ldd, cnt, st), "validate launch");
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, cnt, sizeof h, hipMemcpyDeviceToHost, st), "validate copy");
+    HIP_TRY(hipStreamSynchronize(st), "validate sync");
+    *h_violations = (int64_t)h;
+    if (h) return fail(APSP_E_INPUT, "%llu entries violate the input contract", h);
+    return APSP_OK;
+}
+
+apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void* data,
+                           const int64_t* d_offsets, const int32_t* d_sizes, const int32_t* h_sizes,
+                           const apsp_opts_t* opts, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_ctx(ctx)) || (rc = check_dtype(dt))) return rc;
+    (void)data; (void)d_offsets; (void)d_sizes; (void)h_sizes; (void)opts; (void)stream; (void)count;
+    return fail(APSP_E_UNSUPPORTED, "apsp_batched is not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Internal declarations shared by the HIP translation units of libapsp.
+// Not installed; the public interface is include/apsp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apsp {
+
+enum DType : int32_t { I32 = 0, F32 = 1 };
+
+constexpr uint32_t kInfI32 = 1u << 30;
+
+// One min-plus product C <- min(C, A (min,+) B) over a rectangular window.
+// Optional exclusion bands remove a run of tile rows / tile columns from the
+// launch (blocked FW excludes the pivot band from its panel and remainder
+// updates).  With ksplit > 1 the reduction dimension is cut into chunks of
+// kchunk elements and the partial minima are merged with atomic min.
+struct GemmProblem {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    int32_t skip_m0, skip_mc;   // first excluded tile row, number excluded
+    int32_t skip_n0, skip_nc;   // first excluded tile column, number excluded
+    int32_t tiles_m, tiles_n;   // tiles launched (after exclusion)
+    int32_t ksplit, kchunk;
+    int32_t wg_begin;           // first workgroup of this problem in the launch
+    int32_t pad_;
+};
+
+constexpr int kMaxGroup = 2;
+
+// Up to kMaxGroup independent products in one launch.
+struct GemmGroup {
+    GemmProblem p[kMaxGroup];
+    int32_t count;
+    int32_t total_wgs;
+};
+
+enum Tile : int32_t { TILE_128 = 1, TILE_64 = 2 };
+
+struct TileShape { int mt, nt, kt; };
+TileShape tile_shape(int tile);
+
+// Fills tiles/wg fields of every problem and the group total for `tile`.
+// split_target: desired number of workgroups (0 disables split-K).
+void finalize_group(GemmGroup& g, int tile, int split_target);
+
+hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, hipStream_t s);
+
+// Closure of an s x s diagonal block (s <= 128) held at D (leading dim ld).
+// kind: 1 = Eq. 1 k-loop, 2 = squaring to a fixpoint.
+hipError_t launch_closure(DType dt, int kind, void* D, int64_t ld, int32_t s, hipStream_t st);
+
+// Counts contract violations into *d_count (uint64, pre-zeroed by the kernel
+// launcher on the same stream).
+hipError_t launch_validate(DType dt, const void* D, int64_t n, int64_t ld,
+                           unsigned long long* d_count, hipStream_t st);
+
+// Fill kernel used instead of hipMemsetAsync for small device counters.
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
+
+// One min-plus squaring pass D <- min(D, D (min,+) D) with change detection:
+// *d_changed is set to 1 when any entry decreased.
+hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld,
+                              uint32_t* d_changed, hipStream_t st);
+
+}  // namespace apsp

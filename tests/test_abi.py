@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/apsp.h declares, and rejects bad arguments before touching
+the device."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "apsp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("minplus_gemm", "apsp_fw", "apsp_rkleene", "apsp_batched", "apsp_validate"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(native):
+    L = ctypes.CDLL(native.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(native.EXPORTS) == declared_functions()
+
+
+def test_version_and_last_error(native):
+    L = native.lib()
+    assert b"gfx950" in L.apsp_version()
+    assert isinstance(L.apsp_last_error(), bytes)
+
+
+def _call_square(native, name, ctx, dt, n, ptr, ld, opts=None):
+    L = native.lib()
+    o = opts or native.make_opts()
+    return getattr(L, name)(ctx, dt, n, ptr, ld, ctypes.byref(o), None)
+
+
+@pytest.mark.parametrize("name", ["apsp_fw", "apsp_rkleene", "apsp_square", "apsp_solve", "apsp_closure"])
+def test_argument_errors_before_any_device_call(native, name):
+    fake = ctypes.c_void_p(0x1000)
+    assert _call_square(native, name, None, 7, 4, fake, 4) == native.APSP_E_ARG
+    assert "dtype" in native.last_error()
+    assert _call_square(native, name, None, 0, -1, fake, 4) == native.APSP_E_ARG
+    assert "negative" in native.last_error()
+    assert _call_square(native, name, None, 0, 8, fake, 4) == native.APSP_E_ARG
+    assert "ld" in native.last_error()
+    assert _call_square(native, name, None, 0, 8, None, 8) == native.APSP_E_ARG
+    assert "NULL" in native.last_error()
+    bad = native.make_opts()
+    bad.block = 96
+    assert _call_square(native, name, None, 0, 8, fake, 8, bad) == native.APSP_E_ARG
+    assert "block" in native.last_error()
+    # valid arguments but no context
+    assert _call_square(native, name, None, 0, 8, fake, 8) == native.APSP_E_ARG
+    assert "context" in native.last_error()
+
+
+def test_minplus_argument_errors(native):
+    L = native.lib()
+    o = native.make_opts()
+    A, B, C = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
+    f = L.minplus_gemm
+    assert f(None, 0, -1, 2, 2, A, 2, B, 2, C, 2, ctypes.byref(o), None) == native.APSP_E_ARG
+    assert f(None, 0, 2, 2, 2, A, 1, B, 2, C, 2, ctypes.byref(o), None) == native.APSP_E_ARG
+    assert "lda" in native.last_error()
+    assert f(None, 0, 2, 2, 2, A, 2, B, 1, C, 2, ctypes.byref(o), None) == native.APSP_E_ARG
+    assert "ldb" in native.last_error()
+    assert f(None, 0, 2, 2, 2, A, 2, B, 2, C, 1, ctypes.byref(o), None) == native.APSP_E_ARG
+    assert "ldc" in native.last_error()
+    # C overlapping A is rejected (the public product is out of place)
+    assert f(None, 0, 4, 4, 4, A, 4, B, 4, ctypes.c_void_p(0x10008), 4, ctypes.byref(o), None) == native.APSP_E_ARG
+    assert "overlap" in native.last_error()
+    assert f(None, 0, 2, 2, 2, None, 2, B, 2, C, 2, ctypes.byref(o), None) == native.APSP_E_ARG
+    assert f(None, 0, 2, 2, 2, A, 2, B, 2, C, 2, ctypes.byref(o), None) == native.APSP_E_ARG
+    assert "context" in native.last_error()
+
+
+def test_validate_argument_errors(native):
+    L = native.lib()
+    v = ctypes.c_int64(0)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.apsp_validate(None, 0, 4, fake, 4, None, None) == native.APSP_E_ARG
+    assert L.apsp_validate(None, 0, 4, fake, 2, None, ctypes.byref(v)) == native.APSP_E_ARG
+    assert L.apsp_validate(None, 0, 4, fake, 4, None, ctypes.byref(v)) == native.APSP_E_ARG
+
+
+def test_create_rejects_bad_arguments(native):
+    L = native.lib()
+    assert L.apsp_create(None, 0) == native.APSP_E_ARG
+    c = ctypes.c_void_p()
+    assert L.apsp_create(ctypes.byref(c), -1) == native.APSP_E_ARG
+    assert L.apsp_destroy(None) == native.APSP_OK
+
+
+def test_injected_create_failure_reports_hip_error(native):
+    # forced from the host: no device call is made
+    code = ("import ctypes, sys; sys.path.insert(0, %r);"
+            "from paper_2310_03983_amd import apsp as a; c = ctypes.c_void_p();"
+            "r = a.lib().apsp_create(ctypes.byref(c), 0);"
+            "print(r, a.last_error())") % ROOT
+    env = dict(os.environ, APSP_FAULT="create", HIP_VISIBLE_DEVICES="")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    status, msg = out.stdout.split(" ", 1)
+    assert int(status) == native.APSP_E_HIP and "injected" in msg
+
+
+def test_binding_rejects_host_tensors(native):
+    import torch
+    with pytest.raises(TypeError):
+        native.apsp_fw(torch.zeros((4, 4), dtype=torch.int32))
+    with pytest.raises(TypeError):
+        native.apsp_fw(torch.zeros((4, 4), dtype=torch.float64))
