@@ -180,6 +180,30 @@ apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
 apsp_status_t apsp_validate(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                             const void *D, int64_t ldd, void *stream, int64_t *h_violations);
 
+/*
+ * Kernel timing for measurement tools (not needed to compute anything).
+ * While enabled, every kernel the context launches is bracketed by two HIP
+ * events recorded on the launch stream; apsp_profile_read synchronises those
+ * events and returns, per kernel kind, the number of launches, their summed
+ * duration and their summed algorithmic work.  A min-plus term is one
+ * (a + b) followed by one min.  Enabling clears previous records.
+ */
+#define APSP_KERNEL_MINPLUS_128 0   /* min-plus product, 128 x 128 tiles */
+#define APSP_KERNEL_MINPLUS_64  1   /* min-plus product, 64 x 64 tiles */
+#define APSP_KERNEL_CLOSURE     2   /* diagonal-tile closure */
+#define APSP_KERNEL_OTHER       3   /* validation, fills, batched, cost model */
+#define APSP_KERNEL_KINDS       4
+
+typedef struct apsp_kernel_stats {
+    int64_t launches;
+    double  milliseconds;   /* sum of event-timed launch durations */
+    double  terms;          /* sum of min-plus terms (M*N*K per product; s^3 per k-loop closure) */
+    double  bytes;          /* sum of compulsory HBM bytes: operands read once, C read and written once */
+} apsp_kernel_stats_t;
+
+apsp_status_t apsp_profile_enable(apsp_ctx_t *ctx, int32_t on);
+apsp_status_t apsp_profile_read(apsp_ctx_t *ctx, int32_t kind, apsp_kernel_stats_t *out);
+
 #ifdef __cplusplus
 }
 #endif

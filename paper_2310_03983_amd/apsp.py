@@ -29,8 +29,10 @@ FLAG_NO_SPLITK = 1
 EXPORTS = [
     "apsp_create", "apsp_destroy", "apsp_last_error", "apsp_version",
     "minplus_gemm", "apsp_closure", "apsp_fw", "apsp_rkleene", "apsp_square",
-    "apsp_solve", "apsp_batched", "apsp_validate",
+    "apsp_solve", "apsp_batched", "apsp_validate", "apsp_profile_enable", "apsp_profile_read",
 ]
+
+KERNEL_MINPLUS_128, KERNEL_MINPLUS_64, KERNEL_CLOSURE, KERNEL_OTHER = 0, 1, 2, 3
 
 
 class ApspError(RuntimeError):
@@ -44,6 +46,11 @@ class Opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("block", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("closure", ctypes.c_int32), ("cutover", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 6)]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("milliseconds", ctypes.c_double),
+                ("terms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True) -> Opts:
@@ -84,6 +91,8 @@ def lib() -> ctypes.CDLL:
                 getattr(L, name).argtypes = [vp, i32, i64, vp, i64, P(Opts), vp]
             L.apsp_batched.argtypes = [vp, i32, i32, vp, vp, vp, P(i32), P(Opts), vp]
             L.apsp_validate.argtypes = [vp, i32, i64, vp, i64, vp, P(i64)]
+            L.apsp_profile_enable.argtypes = [vp, i32]
+            L.apsp_profile_read.argtypes = [vp, i32, P(KernelStats)]
             for name in EXPORTS:
                 if name not in ("apsp_last_error", "apsp_version"):
                     getattr(L, name).restype = i32
@@ -223,3 +232,15 @@ def apsp_batched(data: torch.Tensor, offsets: torch.Tensor, sizes: torch.Tensor,
     _check(lib().apsp_batched(context(data.device.index), dt, count, data.data_ptr(), offsets.data_ptr(),
                               sizes.data_ptr(), hs, ctypes.byref(o), _stream(data, stream)))
     return data
+
+
+def apsp_profile_enable(on: bool = True, device: int | None = None):
+    """Starts (clearing old records) or stops per-launch event timing."""
+    _check(lib().apsp_profile_enable(context(device), 1 if on else 0))
+
+
+def apsp_profile_read(kind: int, device: int | None = None) -> dict:
+    """Per-kind launch count, summed milliseconds, min-plus terms and bytes."""
+    st = KernelStats()
+    _check(lib().apsp_profile_read(context(device), kind, ctypes.byref(st)))
+    return {"launches": st.launches, "ms": st.milliseconds, "terms": st.terms, "bytes": st.bytes}

@@ -11,6 +11,13 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
+
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double terms, bytes;
+};
 
 struct apsp_ctx {
     int device = 0;
@@ -19,6 +26,10 @@ struct apsp_ctx {
     size_t scratch_bytes = 0;
     void* d_plan = nullptr;         // batched plan table (grown on demand)
     size_t plan_bytes = 0;
+    bool prof = false;              // kernel timing enabled
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
     uint32_t magic = 0x41505350;    // "APSP"
 };
 
@@ -76,6 +87,49 @@ apsp_status_t check_square(int64_t n, const void* D, int64_t ld)
     if (n > 0 && !D) return fail(APSP_E_ARG, "matrix pointer is NULL");
     if (n > 0 && ld < n) return fail(APSP_E_ARG, "ld = %lld < n = %lld", (long long)ld, (long long)n);
     return APSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// optional kernel timing: events recorded on the launch stream around a launch
+// ---------------------------------------------------------------------------
+hipEvent_t take_event(apsp_ctx_t* ctx)
+{
+    if (ctx->pool_used == ctx->pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->pool.push_back(e);
+    }
+    return ctx->pool[ctx->pool_used++];
+}
+
+template <class F>
+apsp_status_t timed(apsp_ctx_t* ctx, int kind, double terms, double bytes, hipStream_t st, F&& launch)
+{
+    if (!ctx->prof) return launch();
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return launch();
+    hipEventRecord(a, st);
+    apsp_status_t rc = launch();
+    hipEventRecord(b, st);
+    ctx->recs.push_back({kind, a, b, terms, bytes});
+    return rc;
+}
+
+void group_work(const apsp::GemmGroup& g, int tile, double& terms, double& bytes)
+{
+    const apsp::TileShape ts = apsp::tile_shape(tile);
+    terms = bytes = 0;
+    for (int i = 0; i < g.count; ++i) {
+        const apsp::GemmProblem& p = g.p[i];
+        auto excluded = [](int64_t total, int64_t t0, int64_t tc, int64_t w) {
+            if (!tc) return (int64_t)0;
+            return std::min(total, (t0 + tc) * w) - std::min(total, t0 * w);
+        };
+        const double m = (double)(p.M - excluded(p.M, p.skip_m0, p.skip_mc, ts.mt));
+        const double n = (double)(p.N - excluded(p.N, p.skip_n0, p.skip_nc, ts.nt));
+        terms += m * n * (double)p.K;
+        bytes += 4.0 * (m * p.K + (double)p.K * n + 2.0 * m * n);
+    }
 }
 
 const apsp_opts_t* opts_or_default(const apsp_opts_t* o)
@@ -152,8 +206,13 @@ apsp_status_t run_group(apsp_ctx_t* ctx, apsp_dtype_t dt, apsp::GemmGroup& g, co
 {
     if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
     apsp::finalize_group(g, tile, pl.splitk ? 2 * ctx->num_cus : 0);
-    HIP_TRY(apsp::launch_minplus((apsp::DType)dt, tile, g, st), "min-plus launch");
-    return APSP_OK;
+    double terms, bytes;
+    group_work(g, tile, terms, bytes);
+    const int kind = tile == apsp::TILE_64 ? APSP_KERNEL_MINPLUS_64 : APSP_KERNEL_MINPLUS_128;
+    return timed(ctx, kind, terms, bytes, st, [&]() -> apsp_status_t {
+        HIP_TRY(apsp::launch_minplus((apsp::DType)dt, tile, g, st), "min-plus launch");
+        return APSP_OK;
+    });
 }
 
 apsp_status_t run_one(apsp_ctx_t* ctx, apsp_dtype_t dt, const apsp::GemmProblem& p, const Plan& pl,
@@ -177,13 +236,16 @@ apsp_status_t run_two(apsp_ctx_t* ctx, apsp_dtype_t dt, const apsp::GemmProblem&
     return run_group(ctx, dt, g, pl, pick_tile(pl, mm, nn), st);
 }
 
-apsp_status_t closure(apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t s, int kind,
-                      hipStream_t st)
+apsp_status_t closure(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t s,
+                      int kind, hipStream_t st)
 {
     if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
-    HIP_TRY(apsp::launch_closure((apsp::DType)dt, kind, elem(D, dt, off, off, ld), ld, (int32_t)s, st),
-            "closure launch");
-    return APSP_OK;
+    const double terms = (double)s * s * s, bytes = 8.0 * s * s;
+    return timed(ctx, APSP_KERNEL_CLOSURE, terms, bytes, st, [&]() -> apsp_status_t {
+        HIP_TRY(apsp::launch_closure((apsp::DType)dt, kind, elem(D, dt, off, off, ld), ld, (int32_t)s, st),
+                "closure launch");
+        return APSP_OK;
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -200,7 +262,7 @@ apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
     for (int64_t k0 = 0; k0 < n; k0 += b) {
         const int64_t bk = std::min(b, n - k0);
         // phase 1: close the pivot tile
-        apsp_status_t rc = closure(dt, D, ld, off + k0, bk, pl.closure, st);
+        apsp_status_t rc = closure(ctx, dt, D, ld, off + k0, bk, pl.closure, st);
         if (rc) return rc;
         if (bk == n) break;
         // phase 2: row panel R_KJ <- X* (min,+) R_KJ and column panel C_IK <- C_IK (min,+) X*
@@ -234,7 +296,7 @@ apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
 apsp_status_t rk_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
                         const Plan& pl, hipStream_t st)
 {
-    if (n <= pl.block) return closure(dt, D, ld, off, n, pl.closure, st);
+    if (n <= pl.block) return closure(ctx, dt, D, ld, off, n, pl.closure, st);
     if (pl.cutover > 0 && n <= pl.cutover) return fw_window(ctx, dt, D, ld, off, n, pl, st);
     // split point: half, rounded up to a multiple of the leaf size (so every
     // leaf and every sub-view starts on a tile boundary)
@@ -283,11 +345,19 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
     if (n <= 1) return APSP_OK;
     uint32_t* flag = static_cast<uint32_t*>(ctx->d_scratch) + 4;
     int passes = 0;
+    apsp_status_t rc;
     for (;;) {
         if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
         HIP_TRY(apsp::launch_fill_u32(flag, 0u, 1, st), "flag reset");
-        HIP_TRY(apsp::launch_square_pass((apsp::DType)dt, pick_tile(pl, n, n), D, n, ld, flag, st),
-                "squaring pass");
+        const int tile = pick_tile(pl, n, n);
+        const double terms = (double)n * n * n;
+        rc = timed(ctx, tile == apsp::TILE_64 ? APSP_KERNEL_MINPLUS_64 : APSP_KERNEL_MINPLUS_128, terms,
+                   16.0 * n * n, st, [&]() -> apsp_status_t {
+                       HIP_TRY(apsp::launch_square_pass((apsp::DType)dt, tile, D, n, ld, flag, st),
+                               "squaring pass");
+                       return APSP_OK;
+                   });
+        if (rc) return rc;
         uint32_t h = 0;
         HIP_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st), "flag copy");
         HIP_TRY(hipStreamSynchronize(st), "flag sync");
@@ -339,6 +409,7 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     hipDeviceSynchronize();
     if (ctx->d_scratch) hipFree(ctx->d_scratch);
     if (ctx->d_plan) hipFree(ctx->d_plan);
+    for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
     ctx->magic = 0;
     delete ctx;
     return APSP_OK;
@@ -382,7 +453,7 @@ apsp_status_t apsp_closure(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D,
     if (n > 128) return fail(APSP_E_UNSUPPORTED, "closure block n = %lld > 128", (long long)n);
     if (n <= 1) return APSP_OK;
     const Plan pl = resolve(o);
-    return closure(dt, D, ldd, 0, n, pl.closure, static_cast<hipStream_t>(stream));
+    return closure(ctx, dt, D, ldd, 0, n, pl.closure, static_cast<hipStream_t>(stream));
 }
 
 apsp_status_t apsp_fw(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
@@ -468,6 +539,39 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
     if ((rc = check_ctx(ctx)) || (rc = check_dtype(dt))) return rc;
     (void)data; (void)d_offsets; (void)d_sizes; (void)h_sizes; (void)opts; (void)stream; (void)count;
     return fail(APSP_E_UNSUPPORTED, "apsp_batched is not built yet");
+}
+
+apsp_status_t apsp_profile_enable(apsp_ctx_t* ctx, int32_t on)
+{
+    apsp_status_t rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    for (const ProfRec& r : ctx->recs) {
+        hipEventSynchronize(r.b);
+    }
+    ctx->recs.clear();
+    ctx->pool_used = 0;
+    ctx->prof = on != 0;
+    return APSP_OK;
+}
+
+apsp_status_t apsp_profile_read(apsp_ctx_t* ctx, int32_t kind, apsp_kernel_stats_t* out)
+{
+    apsp_status_t rc;
+    if (!out) return fail(APSP_E_ARG, "output is NULL");
+    if (kind < 0 || kind >= APSP_KERNEL_KINDS) return fail(APSP_E_ARG, "kind = %d", kind);
+    if ((rc = check_ctx(ctx))) return rc;
+    *out = apsp_kernel_stats_t{};
+    for (const ProfRec& r : ctx->recs) {
+        if (r.kind != kind) continue;
+        HIP_TRY(hipEventSynchronize(r.b), "profile event sync");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b), "profile elapsed");
+        out->launches += 1;
+        out->milliseconds += ms;
+        out->terms += r.terms;
+        out->bytes += r.bytes;
+    }
+    return APSP_OK;
 }
 
 }  // extern "C"

@@ -18,7 +18,9 @@ base seed S is mix64(S + g).
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -101,17 +103,33 @@ def _edge_mask_rows(seed: int, n: int, p: float, r0: int, r1: int) -> np.ndarray
     return mask
 
 
+def _for_chunks(fn, n, chunk_rows):
+    """Runs fn(r0) for every row chunk; chunks write disjoint rows and every
+    value is counter-based, so threads do not change the output."""
+    starts = list(range(0, n, chunk_rows))
+    workers = min(len(starts), max(1, min(os.cpu_count() or 1, 8)))
+    if workers <= 1:
+        for r0 in starts:
+            fn(r0)
+        return
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fn, starts))
+
+
 def graph_i32(n: int, p: float, lo: int, hi: int, seed: int, chunk_rows: int = 1024) -> np.ndarray:
     """Directed graph, edge i->j (i != j) with probability p, integer cost
     uniform in [lo, hi]; diagonal 0, absent edges INF = 2**30."""
     assert 0 <= lo <= hi < INF_I32
     W = np.full((n, n), INF_I32, dtype=np.int32)
-    for r0 in range(0, n, chunk_rows):
+
+    def rows(r0):
         r1 = min(n, r0 + chunk_rows)
         mask = _edge_mask_rows(seed, n, p, r0, r1)
         ii, jj = np.nonzero(mask)
         x = (ii.astype(np.uint64) + np.uint64(r0)) * np.uint64(n) + jj.astype(np.uint64)
         W[ii + r0, jj] = _uniform_int_np(h_np(seed, WEIGHT, x), lo, hi).astype(np.int32)
+
+    _for_chunks(rows, n, chunk_rows)
     np.fill_diagonal(W, 0)
     return W
 
@@ -120,13 +138,16 @@ def graph_f32(n: int, p: float, lo: float, hi: float, seed: int, chunk_rows: int
     """Same topology stream as graph_i32; cost = float32(lo + (hi-lo)*u),
     u in [0,1) computed in double and rounded once; absent edges +inf."""
     W = np.full((n, n), np.inf, dtype=np.float32)
-    for r0 in range(0, n, chunk_rows):
+
+    def rows(r0):
         r1 = min(n, r0 + chunk_rows)
         mask = _edge_mask_rows(seed, n, p, r0, r1)
         ii, jj = np.nonzero(mask)
         x = (ii.astype(np.uint64) + np.uint64(r0)) * np.uint64(n) + jj.astype(np.uint64)
         w = lo + (hi - lo) * u01_np(h_np(seed, WEIGHT, x))
         W[ii + r0, jj] = w.astype(np.float32)
+
+    _for_chunks(rows, n, chunk_rows)
     np.fill_diagonal(W, 0.0)
     return W
 
