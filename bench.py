@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-graph batched measurement")
+    ap.add_argument("--batched-steps", type=int, default=20)
     return ap.parse_args()
 
 
@@ -61,6 +63,67 @@ def time_steps(torch, fn, inputs, steps, warmup):
         fn(inputs[warmup + s])
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def bench_batched(torch, np, apsp, gg, dev, steps):
+    """512 graphs, n log-uniform in [32, 512], p uniform in [0.02, 0.3], int32
+    costs 1..100: graphs/s of (a) one replayed persistent launch per batch,
+    (b) one launch of the same kernel per graph, (c) one apsp_solve per graph."""
+    batch = gg.batch_ragged()
+    mats = [gg.batch_graph_i32(b) for b in batch]
+    flat, off, sz = gg.pack_batch(mats)
+    flat_d = torch.from_numpy(flat).to(dev)
+    off_d = torch.from_numpy(off).to(dev)
+    sz_d = torch.from_numpy(sz).to(dev)
+    hs = sz.tolist()
+    count = len(mats)
+    terms = float(sum(int(n) ** 3 for n in hs))
+    out = {"workload": "batch512_n32-512_p0.02-0.3_i32", "graphs": count, "sum_n3": terms}
+
+    def run_batched(copies, per_graph=False):
+        for c in copies:
+            apsp.apsp_batched(c, off_d, sz_d, hs, batch_per_graph=per_graph)
+
+    warm = 2
+    copies = [flat_d.clone() for _ in range(steps + warm)]
+    run_batched(copies[:warm])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_batched(copies[warm:])
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    out["persistent_graph_replay"] = {"ms_per_batch": t * 1e3, "graphs_per_s": count / t,
+                                      "updates_per_s": terms / t}
+    # (b) the same kernel, one launch per graph
+    few = max(2, steps // 4)
+    copies = [flat_d.clone() for _ in range(few + 1)]
+    run_batched(copies[:1], per_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_batched(copies[1:], per_graph=True)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / few
+    out["per_graph_launches"] = {"ms_per_batch": t * 1e3, "graphs_per_s": count / t}
+    # (c) the single-graph API once per graph (whole GPU per graph)
+    views = [torch.from_numpy(m).to(dev) for m in mats]
+    pristine = [v.clone() for v in views]
+    for v in views:
+        apsp.apsp_solve(v)
+    torch.cuda.synchronize()
+    for v, p0 in zip(views, pristine):
+        v.copy_(p0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in views:
+        apsp.apsp_solve(v)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["per_graph_solve_calls"] = {"ms_per_batch": t * 1e3, "graphs_per_s": count / t}
+    out["speedup_vs_per_graph_launches"] = out["per_graph_launches"]["ms_per_batch"] / \
+        out["persistent_graph_replay"]["ms_per_batch"]
+    out["speedup_vs_per_graph_solve"] = out["per_graph_solve_calls"]["ms_per_batch"] / \
+        out["persistent_graph_replay"]["ms_per_batch"]
+    return out
 
 
 def counter_traffic():
@@ -204,6 +267,9 @@ def main():
             del ins, src
             torch.cuda.empty_cache()
         result["extras"] = extras
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(torch, np, apsp, gg, dev, args.batched_steps)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")

@@ -72,7 +72,9 @@ typedef int32_t apsp_dtype_t;
 #define APSP_TILE_64      2   /* 64 x 64 output tile per workgroup */
 
 /* Flags (apsp_opts_t.flags). */
-#define APSP_FLAG_NO_SPLITK  1  /* never split the reduction dimension */
+#define APSP_FLAG_NO_SPLITK        1  /* never split the reduction dimension */
+#define APSP_FLAG_BATCH_NO_GRAPH   2  /* apsp_batched: launch directly, no HIP graph */
+#define APSP_FLAG_BATCH_PER_GRAPH  4  /* apsp_batched: one launch per graph */
 
 typedef struct apsp_opts {
     int32_t algo;      /* APSP_ALGO_*; only apsp_solve and apsp_batched read it */
@@ -164,8 +166,15 @@ apsp_status_t apsp_solve(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  * row-major matrices back to back; d_offsets[g] (int64, device) is the
  * element offset of graph g and d_sizes[g] (int32, device) its n; h_sizes is
  * the same sizes on the host (used to plan, never dereferenced on device).
- * Every matrix is overwritten with its distances.  n <= 512 per graph;
- * larger graphs give APSP_E_UNSUPPORTED (use apsp_solve).
+ * Every matrix is overwritten with its distances (Sec. 2, Eq. 1 per graph).
+ * Workgroups of one persistent kernel take whole graphs, largest first, from
+ * an atomic queue; the launch (counter reset + kernel) is captured once per
+ * batch shape in a HIP graph and replayed, with the data pointers updated in
+ * the instantiated graph.  n <= 1024 per graph (APSP_E_UNSUPPORTED beyond:
+ * use apsp_solve).  Flags: APSP_FLAG_BATCH_NO_GRAPH launches directly;
+ * APSP_FLAG_BATCH_PER_GRAPH issues one launch per graph (a baseline).
+ * The context keeps the queue order in device memory it allocates on first
+ * use; calls on one context must not overlap across streams.
  */
 apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
                            void *data, const int64_t *d_offsets, const int32_t *d_sizes,

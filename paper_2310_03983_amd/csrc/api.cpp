@@ -26,6 +26,17 @@ struct apsp_ctx {
     size_t scratch_bytes = 0;
     void* d_plan = nullptr;         // batched plan table (grown on demand)
     size_t plan_bytes = 0;
+    hipStream_t capture = nullptr;  // private stream used only for graph capture
+    // cached batched plan: queue order on the device and the captured launch
+    uint64_t bkey = 0;
+    int32_t bcount = 0;
+    int32_t bdtype = -1;
+    std::vector<int32_t> border;
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    hipGraphNode_t bnode = nullptr;
+    hipKernelNodeParams bparams{};
+    apsp::BatchArgs bargs{};
     bool prof = false;              // kernel timing enabled
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
@@ -391,9 +402,14 @@ apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(APSP_E_HIP, "capture stream creation failed");
+    }
     c->scratch_bytes = 4096;
     hipError_t e = hipMalloc(&c->d_scratch, c->scratch_bytes);
     if (e != hipSuccess) {
+        hipStreamDestroy(c->capture);
         delete c;
         return fail(APSP_E_NOMEM, "scratch allocation: %s", hipGetErrorString(e));
     }
@@ -410,6 +426,9 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     if (ctx->d_scratch) hipFree(ctx->d_scratch);
     if (ctx->d_plan) hipFree(ctx->d_plan);
     for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+    if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
+    if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+    if (ctx->capture) hipStreamDestroy(ctx->capture);
     ctx->magic = 0;
     delete ctx;
     return APSP_OK;
@@ -536,9 +555,140 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
                            const apsp_opts_t* opts, void* stream)
 {
     apsp_status_t rc;
-    if ((rc = check_ctx(ctx)) || (rc = check_dtype(dt))) return rc;
-    (void)data; (void)d_offsets; (void)d_sizes; (void)h_sizes; (void)opts; (void)stream; (void)count;
-    return fail(APSP_E_UNSUPPORTED, "apsp_batched is not built yet");
+    if ((rc = check_dtype(dt))) return rc;
+    const apsp_opts_t* o = opts_or_default(opts);
+    if ((rc = check_opts(o))) return rc;
+    if (count < 0) return fail(APSP_E_ARG, "count = %d is negative", count);
+    if (count > 0 && (!data || !d_offsets || !d_sizes || !h_sizes))
+        return fail(APSP_E_ARG, "NULL batch pointer");
+    for (int32_t g = 0; g < count; ++g) {
+        if (h_sizes[g] < 0) return fail(APSP_E_ARG, "graph %d has n = %d", g, h_sizes[g]);
+        if (h_sizes[g] > apsp::batched_max_n())
+            return fail(APSP_E_UNSUPPORTED, "graph %d has n = %d > %d (use apsp_solve)", g, h_sizes[g],
+                        apsp::batched_max_n());
+    }
+    if ((rc = check_ctx(ctx))) return rc;
+    if (count == 0) return APSP_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+
+    // plan: largest graphs first (longest-processing-time order)
+    uint64_t key = 1469598103934665603ull ^ (uint64_t)dt;
+    for (int32_t g = 0; g < count; ++g) key = (key ^ (uint64_t)(uint32_t)h_sizes[g]) * 1099511628211ull;
+    key ^= (uint64_t)count << 40;
+    if (key != ctx->bkey || count != ctx->bcount || dt != ctx->bdtype) {
+        std::vector<int32_t> order(count);
+        for (int32_t g = 0; g < count; ++g) order[g] = g;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return h_sizes[a] > h_sizes[b]; });
+        const size_t need = (size_t)count * sizeof(int32_t);
+        if (need > ctx->plan_bytes) {
+            HIP_TRY(hipStreamSynchronize(st), "plan sync");
+            if (ctx->d_plan) hipFree(ctx->d_plan);
+            ctx->d_plan = nullptr;
+            ctx->plan_bytes = 0;
+            hipError_t e = hipMalloc(&ctx->d_plan, need);
+            if (e != hipSuccess) return fail(APSP_E_NOMEM, "plan allocation: %s", hipGetErrorString(e));
+            ctx->plan_bytes = need;
+        }
+        ctx->border = std::move(order);
+        HIP_TRY(hipMemcpyAsync(ctx->d_plan, ctx->border.data(), need, hipMemcpyHostToDevice, st), "plan upload");
+        if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
+        if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+        ctx->bexec = nullptr;
+        ctx->bgraph = nullptr;
+        ctx->bnode = nullptr;
+        ctx->bkey = key;
+        ctx->bcount = count;
+        ctx->bdtype = dt;
+    }
+    apsp::BatchArgs a{};
+    a.data = data;
+    a.offsets = d_offsets;
+    a.sizes = d_sizes;
+    a.order = static_cast<const int32_t*>(ctx->d_plan);
+    a.count = count;
+    a.counter = static_cast<uint32_t*>(ctx->d_scratch) + 8;
+    const apsp::DType kdt = (apsp::DType)dt;
+    const int grid = std::min<int>(count, ctx->num_cus * apsp::batched_resident_per_cu(kdt));
+    const double terms = 0.0, bytes = 0.0;
+
+    if (o->flags & APSP_FLAG_BATCH_PER_GRAPH) {
+        // baseline: one launch (of the same kernel) per graph
+        for (int32_t q = 0; q < count; ++q) {
+            apsp::BatchArgs one = a;
+            one.order = a.order + q;
+            one.count = 1;
+            rc = timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
+                HIP_TRY(apsp::launch_batched(kdt, one, 1, st), "per-graph launch");
+                return APSP_OK;
+            });
+            if (rc) return rc;
+        }
+        return APSP_OK;
+    }
+    if (o->flags & APSP_FLAG_BATCH_NO_GRAPH) {
+        return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
+            HIP_TRY(apsp::launch_batched(kdt, a, grid, st), "batched launch");
+            return APSP_OK;
+        });
+    }
+    if (!ctx->bexec) {
+        // capture counter reset + persistent kernel once per batch shape
+        HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t le = apsp::launch_batched(kdt, a, grid, ctx->capture);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(ctx->capture, &g);
+        if (le != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return hip_fail(le, "batched capture launch");
+        }
+        HIP_TRY(ce, "end capture");
+        hipGraphExec_t ex = nullptr;
+        hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            hipGraphDestroy(g);
+            return hip_fail(ie, "graph instantiate");
+        }
+        size_t nn = 0;
+        HIP_TRY(hipGraphGetNodes(g, nullptr, &nn), "graph nodes");
+        std::vector<hipGraphNode_t> nodes(nn);
+        HIP_TRY(hipGraphGetNodes(g, nodes.data(), &nn), "graph nodes");
+        hipGraphNode_t kn = nullptr;
+        hipKernelNodeParams kp{};
+        for (hipGraphNode_t nd : nodes) {
+            hipGraphNodeType ty;
+            if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+            hipKernelNodeParams q{};
+            if (hipGraphKernelNodeGetParams(nd, &q) != hipSuccess) continue;
+            if (q.func == apsp::batched_kernel(kdt)) {
+                kn = nd;
+                kp = q;
+            }
+        }
+        if (!kn) {
+            hipGraphExecDestroy(ex);
+            hipGraphDestroy(g);
+            return fail(APSP_E_HIP, "batched kernel node not found in the captured graph");
+        }
+        ctx->bgraph = g;
+        ctx->bexec = ex;
+        ctx->bnode = kn;
+        ctx->bparams = kp;
+        ctx->bargs = a;
+    } else if (memcmp(&a, &ctx->bargs, sizeof a) != 0) {
+        // same batch shape, new buffers: patch the kernel arguments in place
+        hipKernelNodeParams kp = ctx->bparams;
+        void* args[] = {&a};
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        HIP_TRY(hipGraphExecKernelNodeSetParams(ctx->bexec, ctx->bnode, &kp), "graph node update");
+        ctx->bargs = a;
+    }
+    return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
+        HIP_TRY(hipGraphLaunch(ctx->bexec, st), "graph launch");
+        return APSP_OK;
+    });
 }
 
 apsp_status_t apsp_profile_enable(apsp_ctx_t* ctx, int32_t on)

@@ -1,0 +1,150 @@
+// Many independent graphs of uneven sizes closed in one persistent launch.
+//
+// Every workgroup repeatedly takes the next graph from a queue (one atomic
+// ticket counter; the queue is ordered largest-first on the host, so the long
+// graphs start first and the small ones fill the tail) and solves that graph
+// on its own:
+//   n <= 128: the whole matrix is closed in LDS by the block closure;
+//   n  > 128: blocked Floyd-Warshall (Sec. 2, Eq. 1) with 128-wide rounds --
+//            pivot closure, row/column panel tiles, remainder tiles -- all by
+//            the same workgroup, operands streaming through L2.
+// Workgroups never wait on each other, so the kernel cannot deadlock however
+// many of them are resident; the grid is sized to the resident capacity.
+#include "device.h"
+
+#include <algorithm>
+
+namespace apsp {
+
+namespace {
+
+using dev::kMaxS;
+
+constexpr int kB = 128;                                  // round width
+constexpr int kLdsClose = kMaxS * (kMaxS + 2) * 4;       // closure block
+constexpr int kLdsTile = 2 * 2 * (16 / 2) * (kB + 2) * 8; // A and B staging (pairs)
+constexpr int kLds = kLdsClose > kLdsTile ? kLdsClose : kLdsTile;
+
+// One graph, one workgroup.  Written with a single call site for the block
+// closure and a single call site for the tile product (each inlined once):
+// the work of a round is a list -- panel tiles first, then, after a barrier,
+// remainder tiles -- walked by one loop.
+template <class S, bool VEC>
+__device__ __forceinline__ void solve_graph(typename S::T* D, int n, char* smem)
+{
+    using T = typename S::T;
+    using P = typename S::P;
+    T* X = reinterpret_cast<T*>(smem);
+    auto As = reinterpret_cast<P (*)[8][kB + 2]>(smem);
+    auto Bs = reinterpret_cast<P (*)[8][kB + 2]>(smem + 2 * 8 * (kB + 2) * sizeof(P));
+    const int64_t ld = n;
+    const int nt = (n + kB - 1) / kB;     // n <= 128 is a single round with no tiles
+    for (int kt = 0; kt < nt; ++kt) {
+        const int k0 = kt * kB;
+        const int bk = min(kB, n - k0);
+        T* piv = D + (int64_t)k0 * ld + k0;
+        dev::close_block<S>(piv, ld, bk, X);
+        __syncthreads();
+        const int others = nt - 1;
+        const int npanel = 2 * others;
+        const int nitems = npanel + others * others;
+        for (int it = 0; it < nitems; ++it) {
+            if (it == npanel) __syncthreads();   // remainder reads the updated panels
+            const T* A;
+            const T* B;
+            T* C;
+            int M, N;
+            if (it < npanel) {
+                int t = it >> 1;
+                t += (t >= kt);
+                const int o0 = t * kB, w = min(kB, n - o0);
+                if ((it & 1) == 0) {
+                    // row panel R_KJ <- X* (min,+) R_KJ
+                    A = piv;
+                    B = D + (int64_t)k0 * ld + o0;
+                    C = D + (int64_t)k0 * ld + o0;
+                    M = bk;
+                    N = w;
+                } else {
+                    // column panel C_IK <- C_IK (min,+) X*
+                    A = D + (int64_t)o0 * ld + k0;
+                    B = piv;
+                    C = D + (int64_t)o0 * ld + k0;
+                    M = w;
+                    N = bk;
+                }
+            } else {
+                // remainder D_IJ <- min(D_IJ, C_IK (min,+) R_KJ)
+                const int r = it - npanel;
+                int ti = r / others, tj = r - ti * others;
+                ti += (ti >= kt);
+                tj += (tj >= kt);
+                const int r0 = ti * kB, c0 = tj * kB;
+                A = D + (int64_t)r0 * ld + k0;
+                B = D + (int64_t)k0 * ld + c0;
+                C = D + (int64_t)r0 * ld + c0;
+                M = min(kB, n - r0);
+                N = min(kB, n - c0);
+            }
+            dev::mp_tile<S, kB, kB, 16, 8, 8, VEC>(A, ld, B, ld, C, ld, M, N, 0, 0, 0, bk, false, nullptr, As, Bs);
+        }
+        __syncthreads();
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_batched(BatchArgs a)
+{
+    using T = typename S::T;
+    __shared__ __attribute__((aligned(16))) char smem[kLds];
+    __shared__ int ticket;
+    for (;;) {
+        if (threadIdx.x == 0) ticket = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int q = ticket;
+        __syncthreads();
+        if (q >= a.count) break;
+        const int g = a.order[q];
+        const int n = a.sizes[g];
+        T* D = static_cast<T*>(a.data) + a.offsets[g];
+        const bool vec = (n % 4 == 0) && ((reinterpret_cast<uintptr_t>(D) & 15) == 0);
+        if (vec)
+            solve_graph<S, true>(D, n, smem);
+        else
+            solve_graph<S, false>(D, n, smem);
+    }
+}
+
+}  // namespace
+
+const void* batched_kernel(DType dt)
+{
+    return dt == I32 ? reinterpret_cast<const void*>(&k_batched<dev::SemI32>)
+                     : reinterpret_cast<const void*>(&k_batched<dev::SemF32>);
+}
+
+int batched_max_n() { return 8 * kB; }
+
+hipError_t launch_batched(DType dt, const BatchArgs& a, int grid, hipStream_t st)
+{
+    if (a.count <= 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(a.counter, 0u, 1, st);
+    if (e != hipSuccess) return e;
+    if (dt == I32)
+        hipLaunchKernelGGL(k_batched<dev::SemI32>, dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_batched<dev::SemF32>, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int batched_resident_per_cu(DType dt)
+{
+    int blocks = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, dt == I32 ? reinterpret_cast<const void*>(&k_batched<dev::SemI32>)
+                           : reinterpret_cast<const void*>(&k_batched<dev::SemF32>),
+        256, 0);
+    return (e == hipSuccess && blocks > 0) ? blocks : 1;
+}
+
+}  // namespace apsp

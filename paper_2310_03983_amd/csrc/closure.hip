@@ -3,107 +3,30 @@
 // every round) and R-Kleene (its leaves).
 //
 // k-loop (Sec. 2, Eq. 1): d[i][j] <- min(d[i][j], d[i][k] + d[k][j]) for
-// k = 0..s-1.  Each of 256 lanes keeps an 8 x 8 sub-block (rows ty + 16*i,
-// columns tx + 16*j) in registers; step k only needs row k and column k,
-// which their owners publish into a double-buffered LDS row/column pair
-// after step k-1, so each step costs one barrier.  Row k and column k do not
-// change during step k because d[k][k] = 0.
+// k = 0..s-1, evaluated in the standard blocked order (pivot band, panels,
+// remainder) so that most of the work uses the two-term packed fold; see
+// k_closure_kloop below.
 //
 // Squaring (Sec. 3.2 applied to the block): X <- min(X, X (min,+) X) until no
 // entry changes.  X lives in LDS; each pass computes the new 8 x 8 values in
 // registers, then writes them back after a barrier.
-#include "internal.h"
+#include "device.h"
+
+#include <algorithm>
 
 namespace apsp {
 
 namespace {
 
-struct CI32 {
-    using T = uint32_t;
-    static __device__ __forceinline__ T inf() { return kInfI32; }
-    static __device__ __forceinline__ T relax(T x, T a, T b) { return min(x, a + b); }
-};
-
-struct CF32 {
-    using T = float;
-    static __device__ __forceinline__ T inf() { return __builtin_inff(); }
-    static __device__ __forceinline__ T relax(T x, T a, T b) { return fminf(x, a + b); }
-};
-
-constexpr int kMaxS = 128;
+using dev::kMaxS;
+using CI32 = dev::SemI32;
+using CF32 = dev::SemF32;
 
 template <class S>
 __global__ __launch_bounds__(256) void k_closure_kloop(typename S::T* __restrict__ D, int64_t ld, int s)
 {
-    using T = typename S::T;
-    __shared__ T rowbuf[2][kMaxS];
-    __shared__ T colbuf[2][kMaxS];
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-
-    T x[8][8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int r = ty + 16 * i;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int c = tx + 16 * j;
-            x[i][j] = (r < s && c < s) ? D[(int64_t)r * ld + c] : S::inf();
-        }
-    }
-    if (ty == 0) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) rowbuf[0][tx + 16 * j] = x[0][j];
-    }
-    if (tx == 0) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) colbuf[0][ty + 16 * i] = x[i][0];
-    }
-    __syncthreads();
-
-    for (int k = 0; k < s; ++k) {
-        const int b = k & 1;
-        T cv[8], rv[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) cv[i] = colbuf[b][ty + 16 * i];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) rv[j] = rowbuf[b][tx + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) x[i][j] = S::relax(x[i][j], cv[i], rv[j]);
-        const int kn = k + 1;
-        if (kn < s) {
-            const int sub = kn >> 4, own = kn & 15;
-            if (ty == own) {
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (i == sub) {
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) rowbuf[b ^ 1][tx + 16 * j] = x[i][j];
-                    }
-            }
-            if (tx == own) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (j == sub) {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) colbuf[b ^ 1][ty + 16 * i] = x[i][j];
-                    }
-            }
-        }
-        __syncthreads();
-    }
-
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int r = ty + 16 * i;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int c = tx + 16 * j;
-            if (r < s && c < s) D[(int64_t)r * ld + c] = x[i][j];
-        }
-    }
+    __shared__ __attribute__((aligned(16))) typename S::T X[kMaxS * (kMaxS + 2)];
+    dev::close_block<S>(D, ld, s, X);
 }
 
 template <class S>

@@ -1,0 +1,443 @@
+// Device-side building blocks shared by the min-plus product, the tile
+// closure and the batched kernel: element semantics, the register-blocked
+// min-plus tile and the in-workgroup block closure.
+#pragma once
+
+#include "internal.h"
+
+namespace apsp {
+namespace dev {
+
+constexpr int kMaxS = 128;   // largest block closed inside one workgroup
+
+struct SemI32 {
+    using T = uint32_t;
+    using P = uint64_t;
+    static __device__ __forceinline__ T inf() { return kInfI32; }
+    static __device__ __forceinline__ P pack(T lo, T hi) { return ((P)hi << 32) | (P)lo; }
+    static __device__ __forceinline__ P pair(T lo, T hi) { return pack(lo, hi); }
+    // one term: saturation is implicit (operands <= 2^30, accumulator <= INF)
+    static __device__ __forceinline__ T relax(T x, T a, T b) { return min(x, a + b); }
+    static __device__ __forceinline__ T fold(T acc, P a, P b) {
+        P s = a + b;   // two independent 32-bit sums, no carry between halves
+        // written as one three-input min so that the compiler cannot
+        // re-associate consecutive steps into min(lo, hi) pairs (which
+        // costs an extra instruction and a live register per accumulator)
+        T r;
+        asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"((T)s), "v"((T)(s >> 32)));
+        return r;
+    }
+    static __device__ __forceinline__ void atomic_min(T* p, T v) { atomicMin(p, v); }
+};
+
+struct SemF32 {
+    using T = float;
+    using P = float2;
+    static __device__ __forceinline__ T inf() { return __builtin_inff(); }
+    static __device__ __forceinline__ P pack(T lo, T hi) { return make_float2(lo, hi); }
+    static __device__ __forceinline__ P pair(T lo, T hi) { return pack(lo, hi); }
+    static __device__ __forceinline__ T relax(T x, T a, T b) { return fminf(x, a + b); }
+    static __device__ __forceinline__ T fold(T acc, P a, P b) {
+        const T s0 = a.x + b.x, s1 = a.y + b.y;
+        T r;
+        asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(s0), "v"(s1));
+        return r;
+    }
+    // Non-negative binary32 values order like their bit patterns read as
+    // signed integers (+inf = 0x7f800000 is the largest), so an integer
+    // atomic min is an exact float min here.
+    static __device__ __forceinline__ void atomic_min(T* p, T v) {
+        atomicMin(reinterpret_cast<int*>(p), __float_as_int(v));
+    }
+};
+
+template <class P>
+struct alignas(2 * sizeof(P)) Pair2 { P x, y; };
+
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    constexpr int X = 8;
+    const int q = G / X, r = G % X;
+    const int x = b % X, s = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
+template <class S, int MT, int NT, int KT, int TM, int TN>
+struct Cfg {
+    static constexpr int TX = NT / TN;
+    static constexpr int TY = MT / TM;
+    static constexpr int NTHR = TX * TY;
+    static constexpr int KP = KT / 2;
+    static constexpr int GM = TM / 2;       // row groups of 2 per lane
+    static constexpr int GN = TN / 2;
+    static constexpr int SM = MT / GM;      // stride between a lane's row groups
+    static constexpr int SN = NT / GN;
+    static constexpr int PADP = 2;          // pairs of padding per LDS row
+    static constexpr int LDA = MT + PADP;
+    static constexpr int LDB = NT + PADP;
+    // staging work per lane
+    static constexpr int A_VECS = MT * KT / 4;          // float4-sized loads of A
+    static constexpr int B_COMBOS = KP * (NT / 4);      // (pair row, 4 columns) of B
+    static_assert(A_VECS % NTHR == 0, "A staging must divide evenly");
+    static_assert(B_COMBOS % NTHR == 0, "B staging must divide evenly");
+    static constexpr int A_PER = A_VECS / NTHR;
+    static constexpr int B_PER = B_COMBOS / NTHR;
+    static_assert(SM == 2 * TY && SN == 2 * TX, "lane row/col groups must tile the block");
+};
+
+
+// ---------------------------------------------------------------------------
+// One MT x NT output tile of C <- min(C, A (min,+) B) over reduction steps
+// [kbeg, kend), computed by one workgroup of (MT/TM)*(NT/TN) lanes.  A, B and
+// C already point at the (0, 0) element of their windows; m0/n0 are the tile
+// origin.  With atomic_out the tile's partial minimum is merged into C with
+// atomic min (split reduction); otherwise C is read once and written once.
+// As/Bs: LDS staging of 2 x KT/2 x (MT+2) and 2 x KT/2 x (NT+2) pairs.
+// ---------------------------------------------------------------------------
+template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC>
+__device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int64_t lda,
+                                        const typename S::T* __restrict__ B, int64_t ldb,
+                                        typename S::T* C, int64_t ldc, int M, int N,
+                                        int m0, int n0, int kbeg, int kend, bool atomic_out,
+                                        uint32_t* __restrict__ changed,
+                                        typename S::P (*As)[KT / 2][MT + 2],
+                                        typename S::P (*Bs)[KT / 2][NT + 2])
+{
+    using C_ = Cfg<S, MT, NT, KT, TM, TN>;
+    using T = typename S::T;
+    using P = typename S::P;
+    constexpr int KP = C_::KP;
+    const int tid = threadIdx.x;
+    const int tx = tid % C_::TX;
+    const int ty = tid / C_::TX;
+
+    auto row_of = [&](int i) { return (i >> 1) * C_::SM + ty * 2 + (i & 1); };
+    auto col_of = [&](int j) { return (j >> 1) * C_::SN + tx * 2 + (j & 1); };
+
+    // ---- accumulators start at C (or INF for a partial-K split)
+    T acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int r = m0 + row_of(i);
+#pragma unroll
+        for (int j = 0; j < TN; j += 2) {
+            const int c = n0 + col_of(j);
+            if (atomic_out) {
+                acc[i][j] = S::inf();
+                acc[i][j + 1] = S::inf();
+            } else if (VEC && r < M && c + 1 < N) {
+                const auto v = *reinterpret_cast<const Pair2<T>*>(C + (int64_t)r * ldc + c);
+                acc[i][j] = v.x;
+                acc[i][j + 1] = v.y;
+            } else {
+                acc[i][j] = (r < M && c < N) ? C[(int64_t)r * ldc + c] : S::inf();
+                acc[i][j + 1] = (r < M && c + 1 < N) ? C[(int64_t)r * ldc + c + 1] : S::inf();
+            }
+        }
+    }
+
+    // ---- staging registers
+    T ra[C_::A_PER][4];
+    T rb[C_::B_PER][2][4];
+
+    auto load_slice = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < C_::A_PER; ++q) {
+            const int L = tid + q * C_::NTHR;
+            const int row = L / (KT / 4);
+            const int c4 = L % (KT / 4);
+            const int gr = m0 + row;
+            const int gk = k0 + c4 * 4;
+            if (VEC && gr < M && gk + 3 < kend) {
+                const float4 v = *reinterpret_cast<const float4*>(A + (int64_t)gr * lda + gk);
+                ra[q][0] = __builtin_bit_cast(T, v.x);
+                ra[q][1] = __builtin_bit_cast(T, v.y);
+                ra[q][2] = __builtin_bit_cast(T, v.z);
+                ra[q][3] = __builtin_bit_cast(T, v.w);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    ra[q][e] = (gr < M && gk + e < kend) ? A[(int64_t)gr * lda + gk + e] : S::inf();
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < C_::B_PER; ++q) {
+            const int L = tid + q * C_::NTHR;
+            const int p = L / (NT / 4);
+            const int c4 = L % (NT / 4);
+            const int gc = n0 + c4 * 4;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int gk = k0 + 2 * p + h;
+                if (VEC && gk < kend && gc + 3 < N) {
+                    const float4 v = *reinterpret_cast<const float4*>(B + (int64_t)gk * ldb + gc);
+                    rb[q][h][0] = __builtin_bit_cast(T, v.x);
+                    rb[q][h][1] = __builtin_bit_cast(T, v.y);
+                    rb[q][h][2] = __builtin_bit_cast(T, v.z);
+                    rb[q][h][3] = __builtin_bit_cast(T, v.w);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        rb[q][h][e] = (gk < kend && gc + e < N) ? B[(int64_t)gk * ldb + gc + e] : S::inf();
+                }
+            }
+        }
+    };
+
+    auto store_slice = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < C_::A_PER; ++q) {
+            const int L = tid + q * C_::NTHR;
+            const int row = L / (KT / 4);
+            const int c4 = L % (KT / 4);
+            As[buf][c4 * 2][row] = S::pack(ra[q][0], ra[q][1]);
+            As[buf][c4 * 2 + 1][row] = S::pack(ra[q][2], ra[q][3]);
+        }
+#pragma unroll
+        for (int q = 0; q < C_::B_PER; ++q) {
+            const int L = tid + q * C_::NTHR;
+            const int p = L / (NT / 4);
+            const int c4 = L % (NT / 4);
+            Pair2<P> lo, hi;
+            lo.x = S::pack(rb[q][0][0], rb[q][1][0]);
+            lo.y = S::pack(rb[q][0][1], rb[q][1][1]);
+            hi.x = S::pack(rb[q][0][2], rb[q][1][2]);
+            hi.y = S::pack(rb[q][0][3], rb[q][1][3]);
+            *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4]) = lo;
+            *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4 + 2]) = hi;
+        }
+    };
+
+    const int nslices = (kend > kbeg) ? (kend - kbeg + KT - 1) / KT : 0;
+    if (nslices > 0) {
+        load_slice(kbeg);
+        store_slice(0);
+        __syncthreads();
+        for (int s = 0; s < nslices; ++s) {
+            const int cur = s & 1;
+            if (s + 1 < nslices) load_slice(kbeg + (s + 1) * KT);
+            // two pair-steps per iteration: enough independent work to hide
+            // LDS latency without hoisting every slice read into registers
+#pragma unroll 2
+            for (int p = 0; p < KP; ++p) {
+                P a[TM], b[TN];
+#pragma unroll
+                for (int g = 0; g < C_::GM; ++g) {
+                    const auto v = *reinterpret_cast<const Pair2<P>*>(&As[cur][p][g * C_::SM + ty * 2]);
+                    a[2 * g] = v.x;
+                    a[2 * g + 1] = v.y;
+                }
+#pragma unroll
+                for (int g = 0; g < C_::GN; ++g) {
+                    const auto v = *reinterpret_cast<const Pair2<P>*>(&Bs[cur][p][g * C_::SN + tx * 2]);
+                    b[2 * g] = v.x;
+                    b[2 * g + 1] = v.y;
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
+            }
+            if (s + 1 < nslices) store_slice(cur ^ 1);
+            __syncthreads();
+        }
+    }
+
+    // ---- epilogue
+    bool dec = false;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int r = m0 + row_of(i);
+#pragma unroll
+        for (int j = 0; j < TN; j += 2) {
+            const int c = n0 + col_of(j);
+            if (atomic_out) {
+                if (r < M && c < N && acc[i][j] < S::inf()) S::atomic_min(C + (int64_t)r * ldc + c, acc[i][j]);
+                if (r < M && c + 1 < N && acc[i][j + 1] < S::inf())
+                    S::atomic_min(C + (int64_t)r * ldc + c + 1, acc[i][j + 1]);
+                continue;
+            }
+            if (changed) {
+                // squaring pass: report whether this tile decreased anything
+                if (r < M && c < N && acc[i][j] < C[(int64_t)r * ldc + c]) dec = true;
+                if (r < M && c + 1 < N && acc[i][j + 1] < C[(int64_t)r * ldc + c + 1]) dec = true;
+            }
+            if (VEC && r < M && c + 1 < N) {
+                Pair2<T> v;
+                v.x = acc[i][j];
+                v.y = acc[i][j + 1];
+                *reinterpret_cast<Pair2<T>*>(C + (int64_t)r * ldc + c) = v;
+            } else {
+                if (r < M && c < N) C[(int64_t)r * ldc + c] = acc[i][j];
+                if (r < M && c + 1 < N) C[(int64_t)r * ldc + c + 1] = acc[i][j + 1];
+            }
+        }
+    }
+    if (changed) {
+        // one vector store per wave that saw a decrease
+        if (__builtin_amdgcn_read_exec() && __any(dec) && (tid % warpSize) == 0) atomicOr(changed, 1u);
+    }
+}
+
+// Blocked form of the Eq. 1 k-loop for one block of s <= 128, in one
+// workgroup of 256 lanes.  Lane (ty, tx) owns the 8 x 8 elements at rows
+// ty + 16*i and columns tx + 16*j, kept in registers; LDS mirrors the whole
+// block so that other lanes can read pivot rows and columns.  The k range is
+// cut into four 32-wide pivot bands P.  With this interleaving, band r is
+// exactly register rows/columns {2r, 2r+1} of every lane, so each round has
+// the same shape on every lane:
+//   1. pivot block P x P: the Eq. 1 k-loop over k in P, in place in LDS (row
+//      k and column k do not change during step k), one barrier per step;
+//   2. panels: rows P x other columns <- P* (min,+) panel and other rows x
+//      columns P <- panel (min,+) P*, computed from the pre-update panels,
+//      then written back;
+//   3. remainder: other x other <- min(., column panel (min,+) row panel).
+// Phases 2 and 3 fold two k at a time with the packed 64-bit add / min3 pair
+// used by the product kernel.  Each element is written only by its owner.
+template <class S>
+__device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64_t ld, int s,
+                                            typename S::T* X)
+{
+    using T = typename S::T;
+    constexpr int LDX = kMaxS + 2;          // even: 8-byte aligned row pairs
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+
+    T x[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = ty + 16 * i;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = tx + 16 * j;
+            x[i][j] = (r < s && c < s) ? D[(int64_t)r * ld + c] : S::inf();
+            X[r * LDX + c] = x[i][j];
+        }
+    }
+    __syncthreads();
+
+    const int rounds = (s + 31) / 32;
+    // fully unrolled so that the band's register rows/columns are constants
+#pragma unroll
+    for (int rd = 0; rd < kMaxS / 32; ++rd) {
+        if (rd >= rounds) break;
+        const int p0 = 32 * rd;
+        const int pc = min(32, s - p0);
+        const int i0 = 2 * rd;               // register rows/cols of band rd
+        // ---- 1. pivot block
+        for (int k = p0; k < p0 + pc; ++k) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const T cv = X[(ty + 16 * (i0 + a)) * LDX + k];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const T rv = X[k * LDX + tx + 16 * (i0 + b)];
+                    x[i0 + a][i0 + b] = S::relax(x[i0 + a][i0 + b], cv, rv);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    X[(ty + 16 * (i0 + a)) * LDX + tx + 16 * (i0 + b)] = x[i0 + a][i0 + b];
+            __syncthreads();
+        }
+        // ---- 2. panels (from the pre-update panel values).  Every band is
+        // walked as 16 full pair-steps: entries outside the block are INF in
+        // LDS, so steps past the block edge change nothing.
+        using P = typename S::P;
+        T nr[2][8], nc[8][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) nr[a][j] = x[i0 + a][j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) nc[i][b] = x[i][i0 + b];
+#pragma unroll 2
+        for (int kk = 0; kk < 32; kk += 2) {
+            const int k = p0 + kk;
+            P pa[8], pb[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                pa[i] = *reinterpret_cast<const P*>(&X[(ty + 16 * i) * LDX + k]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                pb[j] = S::pair(X[k * LDX + tx + 16 * j], X[(k + 1) * LDX + tx + 16 * j]);
+            // row panel: P*[row][k..k+1] + R[k..k+1][col]
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) nr[a][j] = S::fold(nr[a][j], pa[i0 + a], pb[j]);
+            // column panel: C[row][k..k+1] + P*[k..k+1][col]
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) nc[i][b] = S::fold(nc[i][b], pa[i], pb[i0 + b]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j == i0 || j == i0 + 1) continue;
+                x[i0 + a][j] = nr[a][j];
+                X[(ty + 16 * (i0 + a)) * LDX + tx + 16 * j] = nr[a][j];
+            }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i == i0 || i == i0 + 1) continue;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                x[i][i0 + b] = nc[i][b];
+                X[(ty + 16 * i) * LDX + tx + 16 * (i0 + b)] = nc[i][b];
+            }
+        }
+        __syncthreads();
+        // ---- 3. remainder: other rows x other columns
+#pragma unroll 2
+        for (int kk = 0; kk < 32; kk += 2) {
+            const int k = p0 + kk;
+            P pa[8], pb[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                pa[i] = *reinterpret_cast<const P*>(&X[(ty + 16 * i) * LDX + k]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                pb[j] = S::pair(X[k * LDX + tx + 16 * j], X[(k + 1) * LDX + tx + 16 * j]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i == i0 || i == i0 + 1) continue;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (j == i0 || j == i0 + 1) continue;
+                    x[i][j] = S::fold(x[i][j], pa[i], pb[j]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i == i0 || i == i0 + 1) continue;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j == i0 || j == i0 + 1) continue;
+                X[(ty + 16 * i) * LDX + tx + 16 * j] = x[i][j];
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = ty + 16 * i;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = tx + 16 * j;
+            if (r < s && c < s) D[(int64_t)r * ld + c] = x[i][j];
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace apsp

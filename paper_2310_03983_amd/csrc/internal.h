@@ -67,4 +67,21 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s
 hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld,
                               uint32_t* d_changed, hipStream_t st);
 
+// Ragged batch: graph g is the n x n row-major matrix at data + offsets[g]
+// (elements), n = sizes[g].  Workgroups take graphs in the order order[0..count).
+struct BatchArgs {
+    void* data;
+    const int64_t* offsets;
+    const int32_t* sizes;
+    const int32_t* order;
+    int32_t count;
+    uint32_t* counter;   // ticket counter, zeroed by launch_batched
+};
+
+// Enqueues the counter reset and the persistent batched kernel.
+hipError_t launch_batched(DType dt, const BatchArgs& a, int grid, hipStream_t st);
+int batched_resident_per_cu(DType dt);
+const void* batched_kernel(DType dt);
+int batched_max_n();
+
 }  // namespace apsp

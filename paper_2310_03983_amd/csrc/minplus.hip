@@ -21,7 +21,7 @@
 // tile indices land on the same XCD (the dispatcher deals workgroups to the
 // 8 XCDs round-robin), then tiles are walked in groups of 8 tile rows so
 // neighbouring workgroups share A rows and B columns in that XCD's L2.
-#include "internal.h"
+#include "device.h"
 
 #include <algorithm>
 
@@ -29,89 +29,21 @@ namespace apsp {
 
 namespace {
 
-struct SemI32 {
-    using T = uint32_t;
-    using P = uint64_t;
-    static __device__ __forceinline__ T inf() { return kInfI32; }
-    static __device__ __forceinline__ P pack(T lo, T hi) { return ((P)hi << 32) | (P)lo; }
-    static __device__ __forceinline__ T fold(T acc, P a, P b) {
-        P s = a + b;   // two independent 32-bit sums, no carry between halves
-        // written as one three-input min so that the compiler cannot
-        // re-associate consecutive steps into min(lo, hi) pairs (which
-        // costs an extra instruction and a live register per accumulator)
-        T r;
-        asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"((T)s), "v"((T)(s >> 32)));
-        return r;
-    }
-    static __device__ __forceinline__ void atomic_min(T* p, T v) { atomicMin(p, v); }
-};
-
-struct SemF32 {
-    using T = float;
-    using P = float2;
-    static __device__ __forceinline__ T inf() { return __builtin_inff(); }
-    static __device__ __forceinline__ P pack(T lo, T hi) { return make_float2(lo, hi); }
-    static __device__ __forceinline__ T fold(T acc, P a, P b) {
-        const T s0 = a.x + b.x, s1 = a.y + b.y;
-        T r;
-        asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(s0), "v"(s1));
-        return r;
-    }
-    // Non-negative binary32 values order like their bit patterns read as
-    // signed integers (+inf = 0x7f800000 is the largest), so an integer
-    // atomic min is an exact float min here.
-    static __device__ __forceinline__ void atomic_min(T* p, T v) {
-        atomicMin(reinterpret_cast<int*>(p), __float_as_int(v));
-    }
-};
-
-template <class P>
-struct alignas(2 * sizeof(P)) Pair2 { P x, y; };
-
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-    constexpr int X = 8;
-    const int q = G / X, r = G % X;
-    const int x = b % X, s = b / X;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
-}
-
-template <class S, int MT, int NT, int KT, int TM, int TN>
-struct Cfg {
-    static constexpr int TX = NT / TN;
-    static constexpr int TY = MT / TM;
-    static constexpr int NTHR = TX * TY;
-    static constexpr int KP = KT / 2;
-    static constexpr int GM = TM / 2;       // row groups of 2 per lane
-    static constexpr int GN = TN / 2;
-    static constexpr int SM = MT / GM;      // stride between a lane's row groups
-    static constexpr int SN = NT / GN;
-    static constexpr int PADP = 2;          // pairs of padding per LDS row
-    static constexpr int LDA = MT + PADP;
-    static constexpr int LDB = NT + PADP;
-    // staging work per lane
-    static constexpr int A_VECS = MT * KT / 4;          // float4-sized loads of A
-    static constexpr int B_COMBOS = KP * (NT / 4);      // (pair row, 4 columns) of B
-    static_assert(A_VECS % NTHR == 0, "A staging must divide evenly");
-    static_assert(B_COMBOS % NTHR == 0, "B staging must divide evenly");
-    static constexpr int A_PER = A_VECS / NTHR;
-    static constexpr int B_PER = B_COMBOS / NTHR;
-    static_assert(SM == 2 * TY && SN == 2 * TX, "lane row/col groups must tile the block");
-};
+using dev::Cfg;
+using dev::SemF32;
+using dev::SemI32;
 
 template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC>
 __global__ __launch_bounds__((MT / TM) * (NT / TN))
 void k_minplus(const GemmGroup G, uint32_t* __restrict__ changed)
 {
-    using C_ = Cfg<S, MT, NT, KT, TM, TN>;
     using T = typename S::T;
     using P = typename S::P;
-    constexpr int KP = C_::KP;
-
-    __shared__ P As[2][KP][C_::LDA];
-    __shared__ P Bs[2][KP][C_::LDB];
+    __shared__ P As[2][KT / 2][MT + 2];
+    __shared__ P Bs[2][KT / 2][NT + 2];
 
     // ---- which problem / split / tile this workgroup owns
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int bid = dev::xcd_remap(blockIdx.x, gridDim.x);
     int pi = 0;
 #pragma unroll
     for (int i = 1; i < kMaxGroup; ++i)
@@ -136,188 +68,12 @@ void k_minplus(const GemmGroup G, uint32_t* __restrict__ changed)
     int tn = tin / gsz;
     if (Pb.skip_mc && tm >= Pb.skip_m0) tm += Pb.skip_mc;
     if (Pb.skip_nc && tn >= Pb.skip_n0) tn += Pb.skip_nc;
-    const int m0 = tm * MT, n0 = tn * NT;
     const int kbeg = split * Pb.kchunk;
     const int kend = min(Pb.K, kbeg + Pb.kchunk);
-    const bool atomic_out = Pb.ksplit > 1;
 
-    const T* __restrict__ A = static_cast<const T*>(Pb.A);
-    const T* __restrict__ B = static_cast<const T*>(Pb.B);
-    T* C = static_cast<T*>(Pb.C);
-    const int64_t lda = Pb.lda, ldb = Pb.ldb, ldc = Pb.ldc;
-    const int M = Pb.M, N = Pb.N;
-
-    const int tid = threadIdx.x;
-    const int tx = tid % C_::TX;
-    const int ty = tid / C_::TX;
-
-    auto row_of = [&](int i) { return (i >> 1) * C_::SM + ty * 2 + (i & 1); };
-    auto col_of = [&](int j) { return (j >> 1) * C_::SN + tx * 2 + (j & 1); };
-
-    // ---- accumulators start at C (or INF for a partial-K split)
-    T acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int r = m0 + row_of(i);
-#pragma unroll
-        for (int j = 0; j < TN; j += 2) {
-            const int c = n0 + col_of(j);
-            if (atomic_out) {
-                acc[i][j] = S::inf();
-                acc[i][j + 1] = S::inf();
-            } else if (VEC && r < M && c + 1 < N) {
-                const auto v = *reinterpret_cast<const Pair2<T>*>(C + (int64_t)r * ldc + c);
-                acc[i][j] = v.x;
-                acc[i][j + 1] = v.y;
-            } else {
-                acc[i][j] = (r < M && c < N) ? C[(int64_t)r * ldc + c] : S::inf();
-                acc[i][j + 1] = (r < M && c + 1 < N) ? C[(int64_t)r * ldc + c + 1] : S::inf();
-            }
-        }
-    }
-
-    // ---- staging registers
-    T ra[C_::A_PER][4];
-    T rb[C_::B_PER][2][4];
-
-    auto load_slice = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < C_::A_PER; ++q) {
-            const int L = tid + q * C_::NTHR;
-            const int row = L / (KT / 4);
-            const int c4 = L % (KT / 4);
-            const int gr = m0 + row;
-            const int gk = k0 + c4 * 4;
-            if (VEC && gr < M && gk + 3 < kend) {
-                const float4 v = *reinterpret_cast<const float4*>(A + (int64_t)gr * lda + gk);
-                ra[q][0] = __builtin_bit_cast(T, v.x);
-                ra[q][1] = __builtin_bit_cast(T, v.y);
-                ra[q][2] = __builtin_bit_cast(T, v.z);
-                ra[q][3] = __builtin_bit_cast(T, v.w);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    ra[q][e] = (gr < M && gk + e < kend) ? A[(int64_t)gr * lda + gk + e] : S::inf();
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < C_::B_PER; ++q) {
-            const int L = tid + q * C_::NTHR;
-            const int p = L / (NT / 4);
-            const int c4 = L % (NT / 4);
-            const int gc = n0 + c4 * 4;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int gk = k0 + 2 * p + h;
-                if (VEC && gk < kend && gc + 3 < N) {
-                    const float4 v = *reinterpret_cast<const float4*>(B + (int64_t)gk * ldb + gc);
-                    rb[q][h][0] = __builtin_bit_cast(T, v.x);
-                    rb[q][h][1] = __builtin_bit_cast(T, v.y);
-                    rb[q][h][2] = __builtin_bit_cast(T, v.z);
-                    rb[q][h][3] = __builtin_bit_cast(T, v.w);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        rb[q][h][e] = (gk < kend && gc + e < N) ? B[(int64_t)gk * ldb + gc + e] : S::inf();
-                }
-            }
-        }
-    };
-
-    auto store_slice = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < C_::A_PER; ++q) {
-            const int L = tid + q * C_::NTHR;
-            const int row = L / (KT / 4);
-            const int c4 = L % (KT / 4);
-            As[buf][c4 * 2][row] = S::pack(ra[q][0], ra[q][1]);
-            As[buf][c4 * 2 + 1][row] = S::pack(ra[q][2], ra[q][3]);
-        }
-#pragma unroll
-        for (int q = 0; q < C_::B_PER; ++q) {
-            const int L = tid + q * C_::NTHR;
-            const int p = L / (NT / 4);
-            const int c4 = L % (NT / 4);
-            Pair2<P> lo, hi;
-            lo.x = S::pack(rb[q][0][0], rb[q][1][0]);
-            lo.y = S::pack(rb[q][0][1], rb[q][1][1]);
-            hi.x = S::pack(rb[q][0][2], rb[q][1][2]);
-            hi.y = S::pack(rb[q][0][3], rb[q][1][3]);
-            *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4]) = lo;
-            *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4 + 2]) = hi;
-        }
-    };
-
-    const int nslices = (kend > kbeg) ? (kend - kbeg + KT - 1) / KT : 0;
-    if (nslices > 0) {
-        load_slice(kbeg);
-        store_slice(0);
-        __syncthreads();
-        for (int s = 0; s < nslices; ++s) {
-            const int cur = s & 1;
-            if (s + 1 < nslices) load_slice(kbeg + (s + 1) * KT);
-            // two pair-steps per iteration: enough independent work to hide
-            // LDS latency without hoisting every slice read into registers
-#pragma unroll 2
-            for (int p = 0; p < KP; ++p) {
-                P a[TM], b[TN];
-#pragma unroll
-                for (int g = 0; g < C_::GM; ++g) {
-                    const auto v = *reinterpret_cast<const Pair2<P>*>(&As[cur][p][g * C_::SM + ty * 2]);
-                    a[2 * g] = v.x;
-                    a[2 * g + 1] = v.y;
-                }
-#pragma unroll
-                for (int g = 0; g < C_::GN; ++g) {
-                    const auto v = *reinterpret_cast<const Pair2<P>*>(&Bs[cur][p][g * C_::SN + tx * 2]);
-                    b[2 * g] = v.x;
-                    b[2 * g + 1] = v.y;
-                }
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
-            }
-            if (s + 1 < nslices) store_slice(cur ^ 1);
-            __syncthreads();
-        }
-    }
-
-    // ---- epilogue
-    bool dec = false;
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int r = m0 + row_of(i);
-#pragma unroll
-        for (int j = 0; j < TN; j += 2) {
-            const int c = n0 + col_of(j);
-            if (atomic_out) {
-                if (r < M && c < N && acc[i][j] < S::inf()) S::atomic_min(C + (int64_t)r * ldc + c, acc[i][j]);
-                if (r < M && c + 1 < N && acc[i][j + 1] < S::inf())
-                    S::atomic_min(C + (int64_t)r * ldc + c + 1, acc[i][j + 1]);
-                continue;
-            }
-            if (changed) {
-                // squaring pass: report whether this tile decreased anything
-                if (r < M && c < N && acc[i][j] < C[(int64_t)r * ldc + c]) dec = true;
-                if (r < M && c + 1 < N && acc[i][j + 1] < C[(int64_t)r * ldc + c + 1]) dec = true;
-            }
-            if (VEC && r < M && c + 1 < N) {
-                Pair2<T> v;
-                v.x = acc[i][j];
-                v.y = acc[i][j + 1];
-                *reinterpret_cast<Pair2<T>*>(C + (int64_t)r * ldc + c) = v;
-            } else {
-                if (r < M && c < N) C[(int64_t)r * ldc + c] = acc[i][j];
-                if (r < M && c + 1 < N) C[(int64_t)r * ldc + c + 1] = acc[i][j + 1];
-            }
-        }
-    }
-    if (changed) {
-        // one vector store per wave that saw a decrease
-        if (__builtin_amdgcn_read_exec() && __any(dec) && (tid % warpSize) == 0) atomicOr(changed, 1u);
-    }
+    dev::mp_tile<S, MT, NT, KT, TM, TN, VEC>(static_cast<const T*>(Pb.A), Pb.lda, static_cast<const T*>(Pb.B),
+                                             Pb.ldb, static_cast<T*>(Pb.C), Pb.ldc, Pb.M, Pb.N, tm * MT, tn * NT,
+                                             kbeg, kend, Pb.ksplit > 1, changed, As, Bs);
 }
 
 template <class S, int MT, int NT, int KT, int TM, int TN>

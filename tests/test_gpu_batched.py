@@ -1,0 +1,99 @@
+"""GPU parity of the batched path: every graph of a ragged batch, solved in
+one persistent launch (replayed from a captured HIP graph), against the CPU
+oracle, bit for bit for int32."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2310_03983_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+INF = 1 << 30
+
+
+def pack(mats, dev):
+    flat, off, sz = gg.pack_batch(mats)
+    return (torch.from_numpy(flat).to(dev), torch.from_numpy(off).to(dev),
+            torch.from_numpy(sz).to(dev), sz.tolist(), off)
+
+
+def unpack(flat_d, off, sizes):
+    torch.cuda.synchronize()
+    flat = flat_d.cpu().numpy()
+    return [flat[o:o + n * n].reshape(n, n) for o, n in zip(off, sizes)]
+
+
+def rand_graph(rng, n, p, lo=1, hi=100, dtype="i32"):
+    if dtype == "i32":
+        W = np.where(rng.random((n, n)) < p, rng.integers(lo, hi + 1, (n, n)), INF).astype(np.int32)
+        np.fill_diagonal(W, 0)
+    else:
+        W = np.where(rng.random((n, n)) < p, rng.uniform(0.1, 10.0, (n, n)), np.inf).astype(np.float32)
+        np.fill_diagonal(W, 0.0)
+    return W
+
+
+def test_batched_edge_sizes(native, dev):
+    rng = np.random.default_rng(900)
+    sizes = [0, 1, 2, 3, 31, 127, 128, 129, 200, 255, 256, 257, 511, 512, 513, 1000, 1024, 5]
+    mats = [rand_graph(rng, n, min(0.5, 3.0 / max(n, 1))) for n in sizes]
+    for flags in ({}, {"graph": False}, {"per_graph": True}):
+        flat, off_d, sz_d, hs, off = pack(mats, dev)
+        kw = {}
+        if flags.get("graph") is False:
+            kw["batch_graph"] = False
+        if flags.get("per_graph"):
+            kw["batch_per_graph"] = True
+        native.apsp_batched(flat, off_d, sz_d, hs, **kw)
+        for W, got in zip(mats, unpack(flat, off, hs)):
+            np.testing.assert_array_equal(got, oracle.fw_i32(W), err_msg=f"n={W.shape[0]} {flags}")
+
+
+def test_batched_f32(native, dev):
+    rng = np.random.default_rng(901)
+    mats = [rand_graph(rng, n, 4.0 / n, dtype="f32") for n in (40, 130, 300, 77)]
+    flat, off_d, sz_d, hs, off = pack(mats, dev)
+    native.apsp_batched(flat, off_d, sz_d, hs)
+    for W, got in zip(mats, unpack(flat, off, hs)):
+        ref = oracle.fw_f64(W.astype(np.float64))
+        assert np.array_equal(np.isinf(got), np.isinf(ref))
+        fin = np.isfinite(ref)
+        assert (np.abs(got[fin] - ref[fin]) <= 1e-5 * ref[fin]).all()
+
+
+def test_batched_graph_replays_and_buffer_swaps(native, dev):
+    # the captured launch is replayed several times, on two different buffers,
+    # with unrelated eager work and synchronisations in between
+    rng = np.random.default_rng(902)
+    mats = [rand_graph(rng, n, 0.05) for n in (64, 300, 129, 513, 33)]
+    refs = [oracle.fw_i32(W) for W in mats]
+    bufs = [pack(mats, dev) for _ in range(2)]
+    for rep in range(4):
+        flat, off_d, sz_d, hs, off = bufs[rep % 2]
+        flat.copy_(torch.from_numpy(gg.pack_batch(mats)[0]).to(dev))
+        native.apsp_batched(flat, off_d, sz_d, hs)
+        junk = torch.arange(1000, device=dev).sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert int(junk) == 499500
+        for ref, got in zip(refs, unpack(flat, off, hs)):
+            np.testing.assert_array_equal(got, ref, err_msg=f"replay {rep}")
+
+
+def test_batched_workload_512(native, dev):
+    batch = gg.batch_ragged()
+    mats = [gg.batch_graph_i32(b) for b in batch]
+    flat, off_d, sz_d, hs, off = pack(mats, dev)
+    native.apsp_batched(flat, off_d, sz_d, hs)
+    got = unpack(flat, off, hs)
+    for b, W, g in zip(batch, mats, got):
+        np.testing.assert_array_equal(g, oracle.fw_i32(W, threads=8), err_msg=f"graph {b.g} n={b.n}")
+
+
+def test_batched_rejects_large_graph(native, dev):
+    W = np.zeros((1025, 1025), np.int32)
+    flat, off_d, sz_d, hs, off = pack([W], dev)
+    with pytest.raises(native.ApspError) as e:
+        native.apsp_batched(flat, off_d, sz_d, hs)
+    assert e.value.status == native.APSP_E_UNSUPPORTED
