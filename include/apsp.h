@@ -190,6 +190,65 @@ apsp_status_t apsp_validate(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                             const void *D, int64_t ldd, void *stream, int64_t *h_violations);
 
 /*
+ * Candidate plans.  A fixed table of (algorithm, round width / leaf size,
+ * tile, closure, cutover) choices indexed 0..apsp_candidate_count()-1; the
+ * autotuner times every one of them and the cost model scores them.
+ */
+int32_t apsp_candidate_count(void);
+apsp_status_t apsp_candidate(int32_t index, apsp_opts_t *out);
+
+/*
+ * Cost model: a small MLP, 4 features -> 64 -> 64 -> K (ReLU hidden layers),
+ * whose K outputs are predicted normalised log run times of the K candidate
+ * plans; the plan is the argmin.  Features of a problem, in this order:
+ *   log2(n), log10(density) with density = edges / (n (n-1)) (clamped to
+ *   1e-9), log2(graphs in the batch), 1 if the graph is weakly connected
+ *   else 0.
+ * Parameters are one fp32 array, row-major input x output:
+ *   W1[4][64] | b1[64] | W2[64][64] | b2[64] | W3[64][K] | b3[K]
+ * (4480 + 65 K floats).  Inputs are standardised inside the kernels with the
+ * stored mean/deviation.  Training is full-batch masked mean squared error
+ * with Adam, run entirely inside one kernel launch; every reduction has a
+ * fixed order, so results are deterministic.  Device pointers (d_*) are
+ * caller-owned; rows <= 4096.  The context owns the parameters, the Adam
+ * moments and a small activation workspace, allocated by apsp_costmodel_init.
+ */
+typedef struct apsp_train_cfg {
+    int32_t steps;     /* Adam steps in this call (>= 1) */
+    float lr, beta1, beta2, eps;
+    int32_t reserved[3];
+} apsp_train_cfg_t;
+
+/* (Re)initialises a K-output model with He-uniform weights from a
+ * counter-based hash of `seed`, zero biases, zero Adam state, identity
+ * standardisation.  K must equal apsp_candidate_count() for apsp_plan. */
+apsp_status_t apsp_costmodel_init(apsp_ctx_t *ctx, int32_t K, uint64_t seed);
+apsp_status_t apsp_costmodel_set_norm(apsp_ctx_t *ctx, const float *h_mu4, const float *h_sd4);
+/* Copies count = 4480 + 65 K floats in / out (host memory); set resets Adam. */
+apsp_status_t apsp_costmodel_set_params(apsp_ctx_t *ctx, const float *h_params, int64_t count);
+apsp_status_t apsp_costmodel_get_params(apsp_ctx_t *ctx, float *h_params, int64_t count);
+/* d_X rows x 4, d_T and d_mask rows x K (mask 1 = target present).  d_losses
+ * (steps floats, may be NULL) receives the loss before each step. */
+apsp_status_t apsp_costmodel_train(apsp_ctx_t *ctx, const float *d_X, const float *d_T, const float *d_mask,
+                                   int32_t rows, const apsp_train_cfg_t *cfg, float *d_losses, void *stream);
+/* Gradient of the loss at the current parameters (no update) into d_grad
+ * (4480 + 65 K floats) and the loss into *d_loss (may be NULL). */
+apsp_status_t apsp_costmodel_grad(apsp_ctx_t *ctx, const float *d_X, const float *d_T, const float *d_mask,
+                                  int32_t rows, float *d_grad, float *d_loss, void *stream);
+/* d_out rows x K predictions. */
+apsp_status_t apsp_costmodel_forward(apsp_ctx_t *ctx, const float *d_X, int32_t rows, float *d_out, void *stream);
+/* d_choice rows int32: argmin candidate per row (first minimum). */
+apsp_status_t apsp_costmodel_predict(apsp_ctx_t *ctx, const float *d_X, int32_t rows, int32_t *d_choice,
+                                     void *stream);
+
+/* Plan for one problem (synchronous): the cost model's argmin when a model
+ * with K = apsp_candidate_count() is loaded, else a size rule (blocked FW up
+ * to n = 1024, R-Kleene above).  *h_choice (may be NULL) gets the candidate
+ * index, or -1 for the size rule. */
+apsp_status_t apsp_plan(apsp_ctx_t *ctx, int64_t n, double density, int32_t batch, int32_t connected,
+                        apsp_opts_t *out, int32_t *h_choice);
+
+/*
  * Kernel timing for measurement tools (not needed to compute anything).
  * While enabled, every kernel the context launches is bracketed by two HIP
  * events recorded on the launch stream; apsp_profile_read synchronises those

@@ -30,6 +30,9 @@ EXPORTS = [
     "apsp_create", "apsp_destroy", "apsp_last_error", "apsp_version",
     "minplus_gemm", "apsp_closure", "apsp_fw", "apsp_rkleene", "apsp_square",
     "apsp_solve", "apsp_batched", "apsp_validate", "apsp_profile_enable", "apsp_profile_read",
+    "apsp_candidate_count", "apsp_candidate", "apsp_costmodel_init", "apsp_costmodel_set_norm",
+    "apsp_costmodel_set_params", "apsp_costmodel_get_params", "apsp_costmodel_train", "apsp_costmodel_grad",
+    "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan",
 ]
 
 KERNEL_MINPLUS_128, KERNEL_MINPLUS_64, KERNEL_CLOSURE, KERNEL_OTHER = 0, 1, 2, 3
@@ -46,6 +49,11 @@ class Opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("block", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("closure", ctypes.c_int32), ("cutover", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 6)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
 
 
 class KernelStats(ctypes.Structure):
@@ -95,6 +103,18 @@ def lib() -> ctypes.CDLL:
             L.apsp_validate.argtypes = [vp, i32, i64, vp, i64, vp, P(i64)]
             L.apsp_profile_enable.argtypes = [vp, i32]
             L.apsp_profile_read.argtypes = [vp, i32, P(KernelStats)]
+            f32p = P(ctypes.c_float)
+            L.apsp_candidate_count.argtypes = []
+            L.apsp_candidate.argtypes = [i32, P(Opts)]
+            L.apsp_costmodel_init.argtypes = [vp, i32, ctypes.c_uint64]
+            L.apsp_costmodel_set_norm.argtypes = [vp, f32p, f32p]
+            L.apsp_costmodel_set_params.argtypes = [vp, f32p, i64]
+            L.apsp_costmodel_get_params.argtypes = [vp, f32p, i64]
+            L.apsp_costmodel_train.argtypes = [vp, vp, vp, vp, i32, P(TrainCfg), vp, vp]
+            L.apsp_costmodel_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+            L.apsp_costmodel_forward.argtypes = [vp, vp, i32, vp, vp]
+            L.apsp_costmodel_predict.argtypes = [vp, vp, i32, vp, vp]
+            L.apsp_plan.argtypes = [vp, i64, ctypes.c_double, i32, i32, P(Opts), P(i32)]
             for name in EXPORTS:
                 if name not in ("apsp_last_error", "apsp_version"):
                     getattr(L, name).restype = i32
@@ -246,3 +266,87 @@ def apsp_profile_read(kind: int, device: int | None = None) -> dict:
     st = KernelStats()
     _check(lib().apsp_profile_read(context(device), kind, ctypes.byref(st)))
     return {"launches": st.launches, "ms": st.milliseconds, "terms": st.terms, "bytes": st.bytes}
+
+
+# ---------------------------------------------------------------------------
+# candidate plans and the cost model
+# ---------------------------------------------------------------------------
+
+def apsp_candidate_count() -> int:
+    return int(lib().apsp_candidate_count())
+
+
+def apsp_candidate(index: int) -> Opts:
+    o = Opts()
+    _check(lib().apsp_candidate(index, ctypes.byref(o)))
+    return o
+
+
+def mlp_param_count(K: int) -> int:
+    return 4 * 64 + 64 + 64 * 64 + 64 + 64 * K + K
+
+
+def _f32_dev(t: torch.Tensor, name: str):
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 device tensor")
+    return t.data_ptr()
+
+
+def apsp_costmodel_init(K: int, seed: int = 0, device: int | None = None):
+    _check(lib().apsp_costmodel_init(context(device), K, seed))
+
+
+def apsp_costmodel_set_norm(mu, sd, device: int | None = None):
+    m = (ctypes.c_float * 4)(*[float(x) for x in mu])
+    s_ = (ctypes.c_float * 4)(*[float(x) for x in sd])
+    _check(lib().apsp_costmodel_set_norm(context(device), m, s_))
+
+
+def apsp_costmodel_set_params(params, device: int | None = None):
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().apsp_costmodel_set_params(context(device), a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+
+
+def apsp_costmodel_get_params(K: int, device: int | None = None):
+    import numpy as np
+    a = np.empty(mlp_param_count(K), dtype=np.float32)
+    _check(lib().apsp_costmodel_get_params(context(device), a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+    return a
+
+
+def apsp_costmodel_train(X, T, mask, steps=500, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, losses=None, stream=None):
+    cfg = TrainCfg(steps, lr, beta1, beta2, eps)
+    lp = _f32_dev(losses, "losses") if losses is not None else None
+    _check(lib().apsp_costmodel_train(context(X.device.index), _f32_dev(X, "X"), _f32_dev(T, "T"),
+                                      _f32_dev(mask, "mask"), X.shape[0], ctypes.byref(cfg), lp, _stream(X, stream)))
+
+
+def apsp_costmodel_grad(X, T, mask, grad, loss=None, stream=None):
+    lp = _f32_dev(loss, "loss") if loss is not None else None
+    _check(lib().apsp_costmodel_grad(context(X.device.index), _f32_dev(X, "X"), _f32_dev(T, "T"),
+                                     _f32_dev(mask, "mask"), X.shape[0], _f32_dev(grad, "grad"), lp,
+                                     _stream(X, stream)))
+
+
+def apsp_costmodel_forward(X, out, stream=None):
+    _check(lib().apsp_costmodel_forward(context(X.device.index), _f32_dev(X, "X"), X.shape[0],
+                                        _f32_dev(out, "out"), _stream(X, stream)))
+    return out
+
+
+def apsp_costmodel_predict(X, choice, stream=None):
+    if not choice.is_cuda or choice.dtype != torch.int32:
+        raise TypeError("choice must be an int32 device tensor")
+    _check(lib().apsp_costmodel_predict(context(X.device.index), _f32_dev(X, "X"), X.shape[0],
+                                        choice.data_ptr(), _stream(X, stream)))
+    return choice
+
+
+def apsp_plan(n: int, density: float, batch: int = 1, connected: bool = True, device: int | None = None):
+    """Returns (Opts, candidate index or -1 for the built-in size rule)."""
+    o = Opts()
+    ch = ctypes.c_int32(-1)
+    _check(lib().apsp_plan(context(device), n, float(density), batch, 1 if connected else 0,
+                           ctypes.byref(o), ctypes.byref(ch)))
+    return o, int(ch.value)

@@ -1,0 +1,289 @@
+"""Exhaustive autotuner and cost-model trainer.
+
+    python -m paper_2310_03983_amd.autotune sweep --db timings.json [--first G0 --last G1]
+    python -m paper_2310_03983_amd.autotune train --db timings.json --model model.json
+    python -m paper_2310_03983_amd.autotune evaluate --db timings.json --model model.json
+
+`sweep` times every candidate plan of the library (apsp_candidate) on every
+graph of the 200-graph sweep workload (n log-uniform in [64, 32768], p
+log-uniform in [5e-4, 0.5], half of them chained to be weakly connected),
+with HIP events around each solve on a fresh copy of the input, and appends
+the medians to a JSON timing database (resumable: graphs already timed with
+the same candidate table are skipped).  Every candidate's result is compared
+bit for bit with the first candidate's; disagreement is recorded.
+
+`train` fits the cost-model MLP on the GPU through apsp_costmodel_train:
+inputs are the four plan features, targets the log run times of the
+candidates, standardised with one global mean/deviation (so the per-row
+argmin is unchanged).  `evaluate` reports, on held-out graphs, the regret
+t(pick)/t(best) - 1 of the model's pick against exhaustive tuning, next to
+the best single static candidate and the library's size rule.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import graphgen as gg
+
+DB_VERSION = 1
+
+
+# ---------------------------------------------------------------------------
+# plan features
+# ---------------------------------------------------------------------------
+
+def weakly_connected(W: np.ndarray, inf=gg.INF_I32, chunk_rows: int = 1024) -> bool:
+    """True when the graph is connected ignoring edge directions; edges are
+    merged a row chunk at a time and the scan stops once one component is
+    left."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    n = W.shape[0]
+    if n <= 1:
+        return True
+    labels = np.arange(n)
+    for r0 in range(0, n, chunk_rows):
+        r1 = min(n, r0 + chunk_rows)
+        blk = W[r0:r1]
+        ii, jj = np.nonzero((blk < inf) if np.issubdtype(blk.dtype, np.integer) else np.isfinite(blk))
+        a = labels[ii + r0]
+        b = labels[jj]
+        keep = a != b
+        if not keep.any():
+            continue
+        a, b = a[keep], b[keep]
+        g = coo_matrix((np.ones(a.size, np.int8), (a, b)), shape=(n, n))
+        _, comp = connected_components(g, directed=True, connection="weak")
+        labels = comp[labels]
+        if np.unique(labels).size == 1:
+            return True
+    return np.unique(labels).size == 1
+
+
+def features(W: np.ndarray, batch: int = 1) -> list[float]:
+    """(log2 n, log10 density, log2 batch, weakly connected) of one graph."""
+    n = W.shape[0]
+    if np.issubdtype(W.dtype, np.integer):
+        m = int(np.count_nonzero(W < gg.INF_I32)) - n
+    else:
+        m = int(np.count_nonzero(np.isfinite(W))) - n
+    dens = m / max(1, n * (n - 1))
+    return [math.log2(max(n, 1)), math.log10(max(dens, 1e-9)), math.log2(max(batch, 1)),
+            1.0 if weakly_connected(W) else 0.0]
+
+
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
+
+def candidate_table(apsp):
+    out = []
+    for i in range(apsp.apsp_candidate_count()):
+        o = apsp.apsp_candidate(i)
+        out.append({"algo": o.algo, "block": o.block, "tile": o.tile, "closure": o.closure, "cutover": o.cutover})
+    return out
+
+
+def time_candidate(torch, apsp, Wd, opts, budget_s=0.3, max_reps=15):
+    """Median seconds of apsp_solve(opts) on fresh copies of Wd; returns
+    (median, result of the last run).  Small problems get one untimed
+    warm-up; large ones (n >= 8192, seconds per solve) time every run."""
+    D = Wd.clone()
+    if Wd.shape[0] < 8192:
+        apsp.apsp_solve(D, opts=opts)
+        torch.cuda.synchronize()
+    times = []
+    while True:
+        D.copy_(Wd)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        apsp.apsp_solve(D, opts=opts)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        if len(times) >= max_reps or (len(times) >= 2 and sum(times) >= budget_s):
+            break
+    return float(np.median(times)), D
+
+
+def load_db(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            db = json.load(f)
+        if db.get("version") == DB_VERSION:
+            return db
+    return {"version": DB_VERSION, "records": {}}
+
+
+def save_db(db, path):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=0)
+    os.replace(tmp, path)
+
+
+def sweep(db_path, first=0, last=199, progress=print):
+    import torch
+    from . import apsp
+    dev = torch.device("cuda:0")
+    db = load_db(db_path)
+    cands = candidate_table(apsp)
+    if db.get("candidates") not in (None, cands):
+        db = {"version": DB_VERSION, "records": {}}
+    db["candidates"] = cands
+    db["device"] = torch.cuda.get_device_name(0)
+    graphs = gg.sweep()
+    for sg in graphs[first:last + 1]:
+        key = str(sg.g)
+        if key in db["records"]:
+            continue
+        t0 = time.time()
+        W = gg.sweep_graph_i32(sg)
+        feats = features(W)
+        Wd = torch.from_numpy(W).to(dev)
+        del W
+        times, agree, ref = [], True, None
+        for i in range(len(cands)):
+            t, D = time_candidate(torch, apsp, Wd, apsp.apsp_candidate(i))
+            times.append(t)
+            if ref is None:
+                ref = D
+            else:
+                agree = agree and bool(torch.equal(ref, D))
+                del D
+        db["records"][key] = {"g": sg.g, "n": sg.n, "p": sg.p, "chain": sg.chain, "features": feats,
+                              "times": times, "agree": agree}
+        save_db(db, db_path)
+        best = int(np.argmin(times))
+        progress(f"[autotune] graph {sg.g} n={sg.n} p={sg.p:.2e} best={best} "
+                 f"t={times[best] * 1e3:.2f} ms agree={agree} ({time.time() - t0:.1f} s)")
+        del Wd, ref
+        torch.cuda.empty_cache()
+    return db
+
+
+# ---------------------------------------------------------------------------
+# cost model
+# ---------------------------------------------------------------------------
+
+def dataset(db, ids):
+    recs = [db["records"][str(g)] for g in ids if str(g) in db["records"]]
+    X = np.array([r["features"] for r in recs], dtype=np.float32)
+    L = np.log(np.array([r["times"] for r in recs], dtype=np.float64))
+    return recs, X, L
+
+
+def train(db, ids, steps=3000, lr=3e-3, seed=0):
+    import torch
+    from . import apsp
+    dev = torch.device("cuda:0")
+    recs, X, L = dataset(db, ids)
+    K = L.shape[1]
+    mu = X.mean(axis=0)
+    sd = X.std(axis=0)
+    sd[sd < 1e-6] = 1.0
+    lmu, lsd = float(L.mean()), float(L.std() or 1.0)
+    T = ((L - lmu) / lsd).astype(np.float32)
+    M = np.ones_like(T)
+    apsp.apsp_costmodel_init(K, seed)
+    apsp.apsp_costmodel_set_norm(mu, sd)
+    losses = torch.empty(steps, dtype=torch.float32, device=dev)
+    apsp.apsp_costmodel_train(torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev),
+                              torch.from_numpy(M).to(dev), steps=steps, lr=lr, losses=losses)
+    torch.cuda.synchronize()
+    h = losses.cpu().numpy()
+    return {"version": DB_VERSION, "K": K, "mu": mu.tolist(), "sd": sd.tolist(), "log_mu": lmu, "log_sd": lsd,
+            "params": apsp.apsp_costmodel_get_params(K).tolist(), "candidates": db["candidates"],
+            "train_ids": list(ids), "steps": steps, "lr": lr, "seed": seed,
+            "loss_first": float(h[0]), "loss_last": float(h[-1])}
+
+
+def install(model):
+    """Loads a trained model into the library context (used by apsp_plan)."""
+    from . import apsp
+    apsp.apsp_costmodel_init(model["K"], 0)
+    apsp.apsp_costmodel_set_norm(model["mu"], model["sd"])
+    apsp.apsp_costmodel_set_params(np.asarray(model["params"], dtype=np.float32))
+
+
+def predict(model, X):
+    import torch
+    from . import apsp
+    install(model)
+    dev = torch.device("cuda:0")
+    ch = torch.empty(X.shape[0], dtype=torch.int32, device=dev)
+    apsp.apsp_costmodel_predict(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev), ch)
+    torch.cuda.synchronize()
+    return ch.cpu().numpy()
+
+
+def size_rule(n, cands):
+    """Index of the candidate the library's size rule would run."""
+    want = 1 if n <= 1024 else 2          # blocked FW / R-Kleene, default options
+    for i, c in enumerate(cands):
+        if c["algo"] == want and c["block"] == 128 and c["tile"] == 0 and c["cutover"] == 0 and c["closure"] == 1:
+            return i
+    return 0
+
+
+def evaluate(db, model, test_ids, train_ids):
+    _, Xtr, Ltr = dataset(db, train_ids)
+    recs, X, L = dataset(db, test_ids)
+    T = np.exp(L)
+    best = T.min(axis=1)
+    pick = predict(model, X)
+    # best single static choice on the training graphs (geometric mean of t / t_best)
+    tr_ratio = np.exp(Ltr - Ltr.min(axis=1, keepdims=True))
+    static = int(np.argmin(np.exp(np.log(tr_ratio).mean(axis=0))))
+    rule = np.array([size_rule(r["n"], db["candidates"]) for r in recs])
+
+    def stats(choice):
+        reg = T[np.arange(len(T)), choice] / best - 1.0
+        tot = T[np.arange(len(T)), choice].sum()
+        return {"mean_regret": float(reg.mean()), "max_regret": float(reg.max()),
+                "geomean_ratio": float(np.exp(np.log1p(reg).mean())), "total_s": float(tot),
+                "exact_picks": int((reg == 0).sum())}
+
+    return {"graphs": len(recs), "mlp": stats(pick), "static_best": {"candidate": static, **stats(
+        np.full(len(T), static))}, "size_rule": stats(rule), "exhaustive_total_s": float(best.sum()),
+        "exhaustive_tuning_cost_s": float(T.sum())}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["sweep", "train", "evaluate"])
+    ap.add_argument("--db", required=True)
+    ap.add_argument("--model")
+    ap.add_argument("--first", type=int, default=0)
+    ap.add_argument("--last", type=int, default=199)
+    ap.add_argument("--train-count", type=int, default=150)
+    ap.add_argument("--steps", type=int, default=3000)
+    a = ap.parse_args(argv)
+    if a.cmd == "sweep":
+        sweep(a.db, a.first, a.last, progress=lambda m: print(m, flush=True))
+        return 0
+    db = load_db(a.db)
+    train_ids = list(range(a.train_count))
+    test_ids = list(range(a.train_count, 200))
+    if a.cmd == "train":
+        model = train(db, train_ids, steps=a.steps)
+        with open(a.model, "w") as f:
+            json.dump(model, f)
+        print(json.dumps({k: model[k] for k in ("K", "loss_first", "loss_last", "steps")}))
+        return 0
+    with open(a.model) as f:
+        model = json.load(f)
+    print(json.dumps(evaluate(db, model, test_ids, train_ids), indent=1))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

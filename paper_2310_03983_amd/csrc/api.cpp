@@ -6,6 +6,8 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cmath>
+#include <utility>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -37,6 +39,16 @@ struct apsp_ctx {
     hipGraphNode_t bnode = nullptr;
     hipKernelNodeParams bparams{};
     apsp::BatchArgs bargs{};
+    // cost model
+    int32_t cm_K = 0;
+    float* cm_params = nullptr;     // device: parameters, Adam moments, gradients
+    float* cm_m = nullptr;
+    float* cm_v = nullptr;
+    float* cm_grad = nullptr;
+    float* cm_ws = nullptr;         // activation workspace for kCmMaxRows rows
+    float* cm_io = nullptr;         // plan: 4 features, K outputs, 1 choice
+    int32_t cm_steps = 0;           // Adam steps taken since init / set_params
+    apsp::MlpNorm cm_norm{};
     bool prof = false;              // kernel timing enabled
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
@@ -379,6 +391,45 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
     return APSP_OK;
 }
 
+// Candidate plans scored by the cost model and timed by the autotuner.
+struct Candidate {
+    int32_t algo, block, tile, closure, cutover;
+};
+const Candidate kCandidates[] = {
+    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
+    {APSP_ALGO_FW, 64, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
+    {APSP_ALGO_RKLEENE, 64, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 1024},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_64, APSP_CLOSURE_KLOOP, 0},
+    {APSP_ALGO_SQUARE, 0, APSP_TILE_AUTO, APSP_CLOSURE_AUTO, 0},
+    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_SQUARE, 0},
+};
+constexpr int32_t kNumCandidates = (int32_t)(sizeof(kCandidates) / sizeof(kCandidates[0]));
+constexpr int32_t kCmMaxRows = 4096;
+
+uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void free_costmodel(apsp_ctx_t* c)
+{
+    for (float** p : {&c->cm_params, &c->cm_m, &c->cm_v, &c->cm_grad, &c->cm_ws, &c->cm_io}) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    c->cm_K = 0;
+}
+
+apsp_status_t check_model(apsp_ctx_t* ctx)
+{
+    if (!ctx->cm_params) return fail(APSP_E_STATE, "no cost model: call apsp_costmodel_init first");
+    return APSP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -426,6 +477,7 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     if (ctx->d_scratch) hipFree(ctx->d_scratch);
     if (ctx->d_plan) hipFree(ctx->d_plan);
     for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+    free_costmodel(ctx);
     if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
     if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
     if (ctx->capture) hipStreamDestroy(ctx->capture);
@@ -722,6 +774,203 @@ apsp_status_t apsp_profile_read(apsp_ctx_t* ctx, int32_t kind, apsp_kernel_stats
         out->bytes += r.bytes;
     }
     return APSP_OK;
+}
+
+int32_t apsp_candidate_count(void) { return kNumCandidates; }
+
+apsp_status_t apsp_candidate(int32_t index, apsp_opts_t* out)
+{
+    if (!out) return fail(APSP_E_ARG, "output is NULL");
+    if (index < 0 || index >= kNumCandidates) return fail(APSP_E_ARG, "candidate %d of %d", index, kNumCandidates);
+    *out = apsp_opts_t{};
+    const Candidate& c = kCandidates[index];
+    out->algo = c.algo;
+    out->block = c.block;
+    out->tile = c.tile;
+    out->closure = c.closure;
+    out->cutover = c.cutover;
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_init(apsp_ctx_t* ctx, int32_t K, uint64_t seed)
+{
+    apsp_status_t rc;
+    if (K < 1 || K > 64) return fail(APSP_E_ARG, "K = %d (1..64)", K);
+    if ((rc = check_ctx(ctx))) return rc;
+    HIP_TRY(hipDeviceSynchronize(), "costmodel sync");
+    free_costmodel(ctx);
+    const int np = apsp::mlp_param_count(K);
+    const size_t pb = (size_t)np * sizeof(float);
+    const size_t wb = (size_t)apsp::mlp_workspace_floats(kCmMaxRows, K) * sizeof(float);
+    hipError_t e = hipSuccess;
+    for (auto pr : {std::make_pair(&ctx->cm_params, pb), std::make_pair(&ctx->cm_m, pb),
+                    std::make_pair(&ctx->cm_v, pb), std::make_pair(&ctx->cm_grad, pb),
+                    std::make_pair(&ctx->cm_ws, wb), std::make_pair(&ctx->cm_io, (size_t)(8 + K) * sizeof(float))})
+        if (e == hipSuccess) e = hipMalloc(pr.first, pr.second);
+    if (e != hipSuccess) {
+        free_costmodel(ctx);
+        return fail(APSP_E_NOMEM, "cost model allocation: %s", hipGetErrorString(e));
+    }
+    // He-uniform weights, zero biases
+    std::vector<float> h(np, 0.f);
+    const int H = apsp::kMlpHidden, I = apsp::kMlpIn;
+    const int oW1 = 0, oW2 = I * H + H, oW3 = oW2 + H * H + H;
+    auto fill = [&](int off, int count, int fan_in, uint64_t stream) {
+        const double a = std::sqrt(6.0 / fan_in);
+        const uint64_t key = mix64(seed + stream * 0x9E3779B97F4A7C15ull);
+        for (int i = 0; i < count; ++i) {
+            const double u = (double)(mix64(key + (uint64_t)i) >> 11) * (1.0 / 9007199254740992.0);
+            h[off + i] = (float)(a * (2.0 * u - 1.0));
+        }
+    };
+    fill(oW1, I * H, I, 1);
+    fill(oW2, H * H, H, 2);
+    fill(oW3, H * K, H, 3);
+    HIP_TRY(hipMemcpy(ctx->cm_params, h.data(), pb, hipMemcpyHostToDevice), "params upload");
+    std::vector<float> z(np, 0.f);
+    HIP_TRY(hipMemcpy(ctx->cm_m, z.data(), pb, hipMemcpyHostToDevice), "moment reset");
+    HIP_TRY(hipMemcpy(ctx->cm_v, z.data(), pb, hipMemcpyHostToDevice), "moment reset");
+    ctx->cm_K = K;
+    ctx->cm_steps = 0;
+    for (int i = 0; i < I; ++i) {
+        ctx->cm_norm.mu[i] = 0.f;
+        ctx->cm_norm.sd[i] = 1.f;
+    }
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_set_norm(apsp_ctx_t* ctx, const float* mu, const float* sd)
+{
+    apsp_status_t rc;
+    if (!mu || !sd) return fail(APSP_E_ARG, "NULL normalisation array");
+    for (int i = 0; i < apsp::kMlpIn; ++i)
+        if (!(sd[i] > 0.f)) return fail(APSP_E_ARG, "sd[%d] must be > 0", i);
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    for (int i = 0; i < apsp::kMlpIn; ++i) {
+        ctx->cm_norm.mu[i] = mu[i];
+        ctx->cm_norm.sd[i] = sd[i];
+    }
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_set_params(apsp_ctx_t* ctx, const float* h, int64_t count)
+{
+    apsp_status_t rc;
+    if (!h) return fail(APSP_E_ARG, "NULL parameter array");
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    const int np = apsp::mlp_param_count(ctx->cm_K);
+    if (count != np) return fail(APSP_E_ARG, "count = %lld, model has %d parameters", (long long)count, np);
+    HIP_TRY(hipDeviceSynchronize(), "costmodel sync");
+    HIP_TRY(hipMemcpy(ctx->cm_params, h, (size_t)np * 4, hipMemcpyHostToDevice), "params upload");
+    std::vector<float> z(np, 0.f);
+    HIP_TRY(hipMemcpy(ctx->cm_m, z.data(), (size_t)np * 4, hipMemcpyHostToDevice), "moment reset");
+    HIP_TRY(hipMemcpy(ctx->cm_v, z.data(), (size_t)np * 4, hipMemcpyHostToDevice), "moment reset");
+    ctx->cm_steps = 0;
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_get_params(apsp_ctx_t* ctx, float* h, int64_t count)
+{
+    apsp_status_t rc;
+    if (!h) return fail(APSP_E_ARG, "NULL parameter array");
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    const int np = apsp::mlp_param_count(ctx->cm_K);
+    if (count != np) return fail(APSP_E_ARG, "count = %lld, model has %d parameters", (long long)count, np);
+    HIP_TRY(hipDeviceSynchronize(), "costmodel sync");
+    HIP_TRY(hipMemcpy(h, ctx->cm_params, (size_t)np * 4, hipMemcpyDeviceToHost), "params download");
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_train(apsp_ctx_t* ctx, const float* X, const float* T, const float* M, int32_t rows,
+                                   const apsp_train_cfg_t* cfg, float* losses, void* stream)
+{
+    apsp_status_t rc;
+    if (!X || !T || !M || !cfg) return fail(APSP_E_ARG, "NULL argument");
+    if (rows < 1 || rows > kCmMaxRows) return fail(APSP_E_ARG, "rows = %d (1..%d)", rows, kCmMaxRows);
+    if (cfg->steps < 1) return fail(APSP_E_ARG, "steps = %d", cfg->steps);
+    if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) ||
+        !(cfg->eps > 0.f))
+        return fail(APSP_E_ARG, "bad Adam hyper-parameters");
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    apsp::MlpAdam opt{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, ctx->cm_steps};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = timed(ctx, APSP_KERNEL_OTHER, 0.0, 0.0, st, [&]() -> apsp_status_t {
+        HIP_TRY(apsp::launch_mlp_train(ctx->cm_params, ctx->cm_m, ctx->cm_v, ctx->cm_norm, X, T, M, rows, ctx->cm_K,
+                                       cfg->steps, opt, ctx->cm_ws, ctx->cm_grad, losses, st),
+                "mlp train launch");
+        return APSP_OK;
+    });
+    if (rc == APSP_OK) ctx->cm_steps += cfg->steps;
+    return rc;
+}
+
+apsp_status_t apsp_costmodel_grad(apsp_ctx_t* ctx, const float* X, const float* T, const float* M, int32_t rows,
+                                  float* d_grad, float* d_loss, void* stream)
+{
+    apsp_status_t rc;
+    if (!X || !T || !M || !d_grad) return fail(APSP_E_ARG, "NULL argument");
+    if (rows < 1 || rows > kCmMaxRows) return fail(APSP_E_ARG, "rows = %d (1..%d)", rows, kCmMaxRows);
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    apsp::MlpAdam opt{1.f, 0.9f, 0.999f, 1e-8f, 0};
+    HIP_TRY(apsp::launch_mlp_train(ctx->cm_params, ctx->cm_m, ctx->cm_v, ctx->cm_norm, X, T, M, rows, ctx->cm_K, 0,
+                                   opt, ctx->cm_ws, d_grad, d_loss, st),
+            "mlp grad launch");
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_forward(apsp_ctx_t* ctx, const float* X, int32_t rows, float* d_out, void* stream)
+{
+    apsp_status_t rc;
+    if (!X || !d_out) return fail(APSP_E_ARG, "NULL argument");
+    if (rows < 1 || rows > kCmMaxRows) return fail(APSP_E_ARG, "rows = %d (1..%d)", rows, kCmMaxRows);
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(apsp::launch_mlp_forward(ctx->cm_params, ctx->cm_norm, X, rows, ctx->cm_K, ctx->cm_ws, d_out, st),
+            "mlp forward launch");
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_predict(apsp_ctx_t* ctx, const float* X, int32_t rows, int32_t* d_choice, void* stream)
+{
+    apsp_status_t rc;
+    if (!X || !d_choice) return fail(APSP_E_ARG, "NULL argument");
+    if (rows < 1 || rows > kCmMaxRows) return fail(APSP_E_ARG, "rows = %d (1..%d)", rows, kCmMaxRows);
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // predictions land after the activations in the workspace
+    float* out = ctx->cm_ws + apsp::mlp_workspace_floats(rows, ctx->cm_K) - (int64_t)rows * ctx->cm_K;
+    HIP_TRY(apsp::launch_mlp_forward(ctx->cm_params, ctx->cm_norm, X, rows, ctx->cm_K, ctx->cm_ws, out, st),
+            "mlp forward launch");
+    HIP_TRY(apsp::launch_argmin_rows(out, rows, ctx->cm_K, d_choice, st), "argmin launch");
+    return APSP_OK;
+}
+
+apsp_status_t apsp_plan(apsp_ctx_t* ctx, int64_t n, double density, int32_t batch, int32_t connected,
+                        apsp_opts_t* out, int32_t* h_choice)
+{
+    apsp_status_t rc;
+    if (!out) return fail(APSP_E_ARG, "output is NULL");
+    if (n < 0 || batch < 1 || density < 0.0) return fail(APSP_E_ARG, "bad plan features");
+    if ((rc = check_ctx(ctx))) return rc;
+    if (h_choice) *h_choice = -1;
+    if (!ctx->cm_params || ctx->cm_K != kNumCandidates) {
+        *out = apsp_opts_t{};
+        out->algo = n <= 1024 ? APSP_ALGO_FW : APSP_ALGO_RKLEENE;
+        return APSP_OK;
+    }
+    float x[4] = {(float)std::log2((double)std::max<int64_t>(n, 1)),
+                  (float)std::log10(std::max(density, 1e-9)), (float)std::log2((double)batch),
+                  connected ? 1.f : 0.f};
+    HIP_TRY(hipMemcpy(ctx->cm_io, x, sizeof x, hipMemcpyHostToDevice), "plan features upload");
+    rc = apsp_costmodel_predict(ctx, ctx->cm_io, 1, reinterpret_cast<int32_t*>(ctx->cm_io + 4), nullptr);
+    if (rc) return rc;
+    int32_t choice = 0;
+    HIP_TRY(hipMemcpy(&choice, ctx->cm_io + 4, sizeof choice, hipMemcpyDeviceToHost), "plan choice download");
+    if (choice < 0 || choice >= kNumCandidates) return fail(APSP_E_STATE, "model chose %d", choice);
+    if (h_choice) *h_choice = choice;
+    return apsp_candidate(choice, out);
 }
 
 }  // extern "C"

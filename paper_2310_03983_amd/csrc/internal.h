@@ -84,4 +84,31 @@ int batched_resident_per_cu(DType dt);
 const void* batched_kernel(DType dt);
 int batched_max_n();
 
+// ---- cost-model MLP (mlp.hip)
+constexpr int kMlpIn = 4;
+constexpr int kMlpHidden = 64;
+__host__ __device__ constexpr int mlp_param_count(int K)
+{
+    return kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden * K + K;
+}
+// floats of activation workspace for `rows` rows
+__host__ __device__ constexpr int64_t mlp_workspace_floats(int rows, int K)
+{
+    return (int64_t)rows * (6 * kMlpHidden + K);
+}
+struct MlpNorm {
+    float mu[kMlpIn];
+    float sd[kMlpIn];
+};
+struct MlpAdam {
+    float lr, beta1, beta2, eps;
+    int32_t t0;   // Adam steps already taken (bias-correction offset)
+};
+hipError_t launch_mlp_forward(const float* P, const MlpNorm& nm, const float* X, int rows, int K, float* ws,
+                              float* out, hipStream_t st);
+hipError_t launch_mlp_train(float* P, float* M, float* V, const MlpNorm& nm, const float* X, const float* T,
+                            const float* Msk, int rows, int K, int steps, const MlpAdam& opt, float* ws, float* G,
+                            float* losses, hipStream_t st);
+hipError_t launch_argmin_rows(const float* out, int rows, int K, int32_t* choice, hipStream_t st);
+
 }  // namespace apsp

@@ -120,3 +120,16 @@ def test_binding_rejects_host_tensors(native):
         native.apsp_fw(torch.zeros((4, 4), dtype=torch.int32))
     with pytest.raises(TypeError):
         native.apsp_fw(torch.zeros((4, 4), dtype=torch.float64))
+
+
+def test_candidate_table(native):
+    n = native.apsp_candidate_count()
+    assert n >= 4
+    algos = set()
+    for i in range(n):
+        o = native.apsp_candidate(i)
+        assert o.algo in (1, 2, 3) and o.block in (0, 64, 128)
+        algos.add(o.algo)
+    assert algos == {1, 2, 3}
+    with pytest.raises(native.ApspError):
+        native.apsp_candidate(n)
