@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n16384_p0.01_i32")
     ap.add_argument("--algo", default="rkleene", choices=["rkleene", "fw", "solve"])
+    ap.add_argument("--cutover", type=int, default=4096,
+                    help="R-Kleene: sub-problems of at most this size use blocked FW")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
@@ -192,21 +194,29 @@ def main():
     del calib
     torch.cuda.synchronize()
 
-    # timed region: K solves on resident inputs, kernel events recorded live
-    apsp.apsp_profile_enable(True)
-    log(f"timing {args.steps} steps ({args.algo}) after {args.warmup} warm-up")
+    # timed region: K solves on resident inputs; HIP events bracket only the
+    # dominant kernel (recording every launch would perturb the timing)
+    log(f"timing {args.steps} steps ({args.algo}, cutover {args.cutover}) after {args.warmup} warm-up")
     for s in range(args.warmup):
-        solve(copies[s])
+        solve(copies[s], cutover=args.cutover)
     torch.cuda.synchronize()
-    apsp.apsp_profile_enable(True)          # keep only the timed steps' records
+    apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_128])
     t0 = time.perf_counter()
     for s in range(args.steps):
-        solve(copies[args.warmup + s])
+        solve(copies[args.warmup + s], cutover=args.cutover)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     k128 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_128)
-    k64 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_64)
-    kcl = apsp.apsp_profile_read(apsp.KERNEL_CLOSURE)
+    apsp.apsp_profile_enable(False)
+    # one extra, untimed solve with every launch bracketed: time shares
+    share_in = copies[0]
+    share_in.copy_(Wd)
+    apsp.apsp_profile_enable(True)
+    solve(share_in, cutover=args.cutover)
+    torch.cuda.synchronize()
+    shares = {k: apsp.apsp_profile_read(v) for k, v in (("minplus_128", apsp.KERNEL_MINPLUS_128),
+                                                      ("minplus_64", apsp.KERNEL_MINPLUS_64),
+                                                      ("closure", apsp.KERNEL_CLOSURE))}
     apsp.apsp_profile_enable(False)
 
     ms_per_step = elapsed * 1e3 / args.steps
@@ -227,7 +237,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic (seeded Bernoulli graph generator)",
-        "config": {"workload": f"apsp_{wl.name}_{args.algo}", "n": n, "p": wl.p,
+        "config": {"workload": f"apsp_{wl.name}_{args.algo}", "n": n, "p": wl.p, "cutover": args.cutover,
                    "weights": f"int32 uniform [{int(wl.lo)}, {int(wl.hi)}]", "inf": 2 ** 30,
                    "parallelism": "single GPU"},
         "valu_roofline_frac": 2.0 * value / VALU_PEAK_OPS,
@@ -245,11 +255,7 @@ def main():
             "note": "ops = 2 per min-plus term (add + min); one 64-bit add forms two 32-bit sums and one "
                     "v_min3 folds two terms, so frac can exceed 1 against the 32-bit lane-op peak",
         },
-        "kernel_time_share": {
-            "minplus_128": k128["ms"] / (elapsed * 1e3),
-            "minplus_64": k64["ms"] / (elapsed * 1e3),
-            "closure": kcl["ms"] / (elapsed * 1e3),
-        },
+        "kernel_ms_per_solve": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in shares.items()},
     }
     del copies
     torch.cuda.empty_cache()

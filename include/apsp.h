@@ -157,7 +157,9 @@ apsp_status_t apsp_square(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                           void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
 
 /* Dispatches to apsp_fw / apsp_rkleene / apsp_square per opts->algo; with
- * APSP_ALGO_AUTO (or opts == NULL) the planner (apsp_plan) decides. */
+ * APSP_ALGO_AUTO (or opts == NULL) the size rule decides: blocked FW up to
+ * n = 4096, R-Kleene with a 4096 FW cutover above.  (apsp_plan gives the
+ * cost model's choice for explicit use.) */
 apsp_status_t apsp_solve(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                          void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
 
@@ -243,7 +245,7 @@ apsp_status_t apsp_costmodel_predict(apsp_ctx_t *ctx, const float *d_X, int32_t 
 
 /* Plan for one problem (synchronous): the cost model's argmin when a model
  * with K = apsp_candidate_count() is loaded, else a size rule (blocked FW up
- * to n = 1024, R-Kleene above).  *h_choice (may be NULL) gets the candidate
+ * to n = 4096, R-Kleene with a 4096 FW cutover above).  *h_choice (may be NULL) gets the candidate
  * index, or -1 for the size rule. */
 apsp_status_t apsp_plan(apsp_ctx_t *ctx, int64_t n, double density, int32_t batch, int32_t connected,
                         apsp_opts_t *out, int32_t *h_choice);
@@ -269,6 +271,9 @@ typedef struct apsp_kernel_stats {
     double  bytes;          /* sum of compulsory HBM bytes: operands read once, C read and written once */
 } apsp_kernel_stats_t;
 
+/* on = 0 stops recording, 1 records every kind, any other value is a bit
+ * mask (1 << APSP_KERNEL_*) of the kinds to record -- recording only the
+ * kernel under study keeps the events from perturbing the others. */
 apsp_status_t apsp_profile_enable(apsp_ctx_t *ctx, int32_t on);
 apsp_status_t apsp_profile_read(apsp_ctx_t *ctx, int32_t kind, apsp_kernel_stats_t *out);
 

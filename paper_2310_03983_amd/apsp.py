@@ -256,9 +256,20 @@ def apsp_batched(data: torch.Tensor, offsets: torch.Tensor, sizes: torch.Tensor,
     return data
 
 
-def apsp_profile_enable(on: bool = True, device: int | None = None):
-    """Starts (clearing old records) or stops per-launch event timing."""
-    _check(lib().apsp_profile_enable(context(device), 1 if on else 0))
+def apsp_profile_enable(on: bool = True, kinds=None, device: int | None = None):
+    """Starts (clearing old records) or stops per-launch event timing; with
+    `kinds` (iterable of KERNEL_*) only those kernels are bracketed."""
+    if not on:
+        flag = 0
+    elif kinds is None:
+        flag = 1
+    else:
+        flag = 0
+        for k in kinds:
+            flag |= 1 << k
+        if flag == 1:          # only kind 0: 1 would mean "all kinds"
+            flag = 1 | (1 << 31)
+    _check(lib().apsp_profile_enable(context(device), flag))
 
 
 def apsp_profile_read(kind: int, device: int | None = None) -> dict:

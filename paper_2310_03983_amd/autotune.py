@@ -226,10 +226,14 @@ def predict(model, X):
 
 
 def size_rule(n, cands):
-    """Index of the candidate the library's size rule would run."""
-    want = 1 if n <= 1024 else 2          # blocked FW / R-Kleene, default options
+    """Index of the candidate closest to what the library's size rule runs
+    (blocked FW up to n = 4096, R-Kleene with a FW cutover above)."""
+    if n <= 4096:
+        want = {"algo": 1, "block": 128, "tile": 0, "closure": 1, "cutover": 0}
+    else:
+        want = {"algo": 2, "block": 128, "tile": 0, "closure": 1, "cutover": 1024}
     for i, c in enumerate(cands):
-        if c["algo"] == want and c["block"] == 128 and c["tile"] == 0 and c["cutover"] == 0 and c["closure"] == 1:
+        if c == want:
             return i
     return 0
 

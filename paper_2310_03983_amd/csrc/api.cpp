@@ -50,6 +50,7 @@ struct apsp_ctx {
     int32_t cm_steps = 0;           // Adam steps taken since init / set_params
     apsp::MlpNorm cm_norm{};
     bool prof = false;              // kernel timing enabled
+    uint32_t prof_mask = 0;         // bit k set: record kernels of kind k
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
@@ -128,7 +129,7 @@ hipEvent_t take_event(apsp_ctx_t* ctx)
 template <class F>
 apsp_status_t timed(apsp_ctx_t* ctx, int kind, double terms, double bytes, hipStream_t st, F&& launch)
 {
-    if (!ctx->prof) return launch();
+    if (!ctx->prof || !(ctx->prof_mask & (1u << kind))) return launch();
     hipEvent_t a = take_event(ctx), b = take_event(ctx);
     if (!a || !b) return launch();
     hipEventRecord(a, st);
@@ -181,7 +182,7 @@ char* elem(void* base, apsp_dtype_t dt, int64_t r, int64_t c, int64_t ld)
 
 struct Plan {
     int block;      // FW round width / R-Kleene leaf size
-    int tile;       // GEMM tile for big products
+    int tile;       // GEMM tile (APSP_TILE_AUTO: chosen per product)
     int closure;    // 1 k-loop, 2 squaring
     int cutover;    // R-Kleene -> FW below this size
     bool splitk;
@@ -191,7 +192,7 @@ Plan resolve(const apsp_opts_t* o)
 {
     Plan p;
     p.block = o->block ? o->block : 128;
-    p.tile = o->tile ? o->tile : apsp::TILE_128;
+    p.tile = o->tile;   // APSP_TILE_AUTO (0) lets pick_tile decide per product
     p.closure = o->closure ? o->closure : APSP_CLOSURE_KLOOP;
     p.cutover = o->cutover;
     p.splitk = !(o->flags & APSP_FLAG_NO_SPLITK);
@@ -219,8 +220,11 @@ apsp::GemmProblem make_problem(apsp_dtype_t dt, void* base, int64_t ld,
 int pick_tile(const Plan& pl, int64_t M, int64_t N)
 {
     if (pl.tile == apsp::TILE_64) return apsp::TILE_64;
+    if (pl.tile == apsp::TILE_128) return apsp::TILE_128;
+    // 128 x 128 tiles (with a split reduction below 512 tiles) from about
+    // 2048 x 2048 up; 64 x 64 tiles fill the device better below that
     const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
-    if (t128 < 512) return apsp::TILE_64;
+    if (t128 < 256) return apsp::TILE_64;
     return apsp::TILE_128;
 }
 
@@ -573,11 +577,15 @@ apsp_status_t apsp_solve(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, i
     case APSP_ALGO_FW: return apsp_fw(ctx, dt, n, D, ldd, o, stream);
     case APSP_ALGO_SQUARE: return apsp_square(ctx, dt, n, D, ldd, o, stream);
     case APSP_ALGO_RKLEENE: return apsp_rkleene(ctx, dt, n, D, ldd, o, stream);
-    default:
+    default: {
         // R-Kleene's top-level products are large and efficient; blocked FW
-        // has fewer launches on small graphs
-        if (n <= 1024) return apsp_fw(ctx, dt, n, D, ldd, o, stream);
-        return apsp_rkleene(ctx, dt, n, D, ldd, o, stream);
+        // has fewer launches and wins up to about n = 4096, so it also closes
+        // R-Kleene's sub-problems of that size
+        if (n <= 4096) return apsp_fw(ctx, dt, n, D, ldd, o, stream);
+        apsp_opts_t o2 = *o;
+        if (!o2.cutover) o2.cutover = 4096;
+        return apsp_rkleene(ctx, dt, n, D, ldd, &o2, stream);
+    }
     }
 }
 
@@ -753,6 +761,7 @@ apsp_status_t apsp_profile_enable(apsp_ctx_t* ctx, int32_t on)
     ctx->recs.clear();
     ctx->pool_used = 0;
     ctx->prof = on != 0;
+    ctx->prof_mask = (on == 1) ? 0xffffffffu : (uint32_t)on;
     return APSP_OK;
 }
 
@@ -957,7 +966,8 @@ apsp_status_t apsp_plan(apsp_ctx_t* ctx, int64_t n, double density, int32_t batc
     if (h_choice) *h_choice = -1;
     if (!ctx->cm_params || ctx->cm_K != kNumCandidates) {
         *out = apsp_opts_t{};
-        out->algo = n <= 1024 ? APSP_ALGO_FW : APSP_ALGO_RKLEENE;
+        out->algo = n <= 4096 ? APSP_ALGO_FW : APSP_ALGO_RKLEENE;
+        out->cutover = n <= 4096 ? 0 : 4096;
         return APSP_OK;
     }
     float x[4] = {(float)std::log2((double)std::max<int64_t>(n, 1)),

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
         const int g = a.order[q];
         const int n = a.sizes[g];
         T* D = static_cast<T*>(a.data) + a.offsets[g];
-        const bool vec = (n % 4 == 0) && ((reinterpret_cast<uintptr_t>(D) & 15) == 0);
+        const bool vec = (reinterpret_cast<uintptr_t>(D) & 3) == 0;
         if (vec)
             solve_graph<S, true>(D, n, smem);
         else

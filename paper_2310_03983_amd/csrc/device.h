@@ -54,6 +54,23 @@ struct SemF32 {
 template <class P>
 struct alignas(2 * sizeof(P)) Pair2 { P x, y; };
 
+// Global-memory vector access that assumes only element (4-byte) alignment:
+// rows of a matrix with a leading dimension that is not a multiple of 4 start
+// at any 4-byte boundary.  The compiler still emits one dwordx4 / dwordx2
+// access (multi-dword accesses need dword alignment only).
+template <class V, class T>
+__device__ __forceinline__ V ld_vec(const T* p)
+{
+    V v;
+    __builtin_memcpy(&v, p, sizeof(V));
+    return v;
+}
+template <class V, class T>
+__device__ __forceinline__ void st_vec(T* p, const V& v)
+{
+    __builtin_memcpy(p, &v, sizeof(V));
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int G) {
     constexpr int X = 8;
     const int q = G / X, r = G % X;
@@ -125,7 +142,7 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
                 acc[i][j] = S::inf();
                 acc[i][j + 1] = S::inf();
             } else if (VEC && r < M && c + 1 < N) {
-                const auto v = *reinterpret_cast<const Pair2<T>*>(C + (int64_t)r * ldc + c);
+                const auto v = ld_vec<Pair2<T>>(C + (int64_t)r * ldc + c);
                 acc[i][j] = v.x;
                 acc[i][j + 1] = v.y;
             } else {
@@ -148,7 +165,7 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
             const int gr = m0 + row;
             const int gk = k0 + c4 * 4;
             if (VEC && gr < M && gk + 3 < kend) {
-                const float4 v = *reinterpret_cast<const float4*>(A + (int64_t)gr * lda + gk);
+                const float4 v = ld_vec<float4>(A + (int64_t)gr * lda + gk);
                 ra[q][0] = __builtin_bit_cast(T, v.x);
                 ra[q][1] = __builtin_bit_cast(T, v.y);
                 ra[q][2] = __builtin_bit_cast(T, v.z);
@@ -169,7 +186,7 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
             for (int h = 0; h < 2; ++h) {
                 const int gk = k0 + 2 * p + h;
                 if (VEC && gk < kend && gc + 3 < N) {
-                    const float4 v = *reinterpret_cast<const float4*>(B + (int64_t)gk * ldb + gc);
+                    const float4 v = ld_vec<float4>(B + (int64_t)gk * ldb + gc);
                     rb[q][h][0] = __builtin_bit_cast(T, v.x);
                     rb[q][h][1] = __builtin_bit_cast(T, v.y);
                     rb[q][h][2] = __builtin_bit_cast(T, v.z);
@@ -266,7 +283,7 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
                 Pair2<T> v;
                 v.x = acc[i][j];
                 v.y = acc[i][j + 1];
-                *reinterpret_cast<Pair2<T>*>(C + (int64_t)r * ldc + c) = v;
+                st_vec(C + (int64_t)r * ldc + c, v);
             } else {
                 if (r < M && c < N) C[(int64_t)r * ldc + c] = acc[i][j];
                 if (r < M && c + 1 < N) C[(int64_t)r * ldc + c + 1] = acc[i][j + 1];

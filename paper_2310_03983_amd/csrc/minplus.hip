@@ -83,8 +83,9 @@ hipError_t launch_cfg(const GemmGroup& g, uint32_t* changed, hipStream_t st)
     bool vec = true;
     for (int i = 0; i < g.count; ++i) {
         const GemmProblem& p = g.p[i];
-        auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
-        if ((p.lda & 3) || (p.ldb & 3) || (p.ldc & 3) || !al(p.A) || !al(p.B) || !al(p.C)) vec = false;
+        // vector accesses need element (4-byte) alignment only
+        auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 3) == 0; };
+        if (!al(p.A) || !al(p.B) || !al(p.C)) vec = false;
     }
     dim3 grid(g.total_wgs), block(C_::NTHR);
     if (vec)
