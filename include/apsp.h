@@ -164,6 +164,23 @@ apsp_status_t apsp_solve(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                          void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
 
 /*
+ * Last-hop predecessors (Sec. 2: pred[i][j] is the vertex before j on the
+ * i -> j path, recovered by following pred back from j; Sec. 3.1 obtains it
+ * with an argmin over the intermediate index).  From distances D (n x n,
+ * ldd) and costs W (n x n, ldw) of the same dtype, writes the int32 matrix P
+ * (n x n, ldp):
+ *     P[i][j] = the smallest v != j minimising D[i][v] (+) W[v][j],
+ *               -1 when i == j or that minimum is not below INF.
+ * When D is the APSP result of W and every off-diagonal cost is positive
+ * (the paper's assumption), P[i][j] is the last vertex before j on a shortest
+ * i -> j path and following P from j reaches i.  n^3 terms (add, compare,
+ * two selects each).  P must not overlap D or W.
+ */
+apsp_status_t apsp_predecessors(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                                const void *D, int64_t ldd, const void *W, int64_t ldw,
+                                int32_t *P, int64_t ldp, void *stream);
+
+/*
  * Many independent graphs in one launch.  `data` holds `count` square
  * row-major matrices back to back; d_offsets[g] (int64, device) is the
  * element offset of graph g and d_sizes[g] (int32, device) its n; h_sizes is

@@ -76,6 +76,8 @@ def _load():
             lib.oracle_dijkstra_f64.restype = i32
             lib.oracle_certificate_i32.argtypes = [i64, vp, i64, vp, i64, i64, i64, i32]
             lib.oracle_certificate_i32.restype = i64
+            lib.oracle_predecessors_i32.argtypes = [i64, vp, i64, vp, i64, vp, i64, i32]
+            lib.oracle_predecessors_i32.restype = None
             _lib = lib
     return _lib
 
@@ -185,6 +187,36 @@ def certificate_i32(W: np.ndarray, D: np.ndarray, rows=None, threads: int | None
                                               threads or default_threads()))
 
 
+def predecessors_i32(D: np.ndarray, W: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """Last-hop predecessor matrix (smallest v != j minimising D[i][v] (+) W[v][j]; -1 when
+    i == j or unreachable)."""
+    D = np.ascontiguousarray(D, dtype=np.int32)
+    W = np.ascontiguousarray(W, dtype=np.int32)
+    n = D.shape[0]
+    P = np.empty((n, n), dtype=np.int32)
+    _load().oracle_predecessors_i32(n, _ptr(D), n, _ptr(W), n, _ptr(P), n, threads or default_threads())
+    return P
+
+
+def walk_weight(W, P, i, j, inf=INF_I32):
+    """Follows P back from j to i; returns the path's total cost (None when
+    P[i][j] == -1; raises if the walk does not end at i within n steps)."""
+    n = len(W)
+    if i == j:
+        return 0
+    if P[i][j] < 0:
+        return None
+    total, v, steps = 0, j, 0
+    while v != i:
+        u = int(P[i][v])
+        if u < 0 or steps > n:
+            raise AssertionError(f"predecessor walk {i}->{j} broken at {v}")
+        total += int(W[u][v])
+        v = u
+        steps += 1
+    return total
+
+
 # ---------------------------------------------------------------------------
 # Pure-Python references for tiny inputs
 # ---------------------------------------------------------------------------
@@ -222,6 +254,26 @@ def brute_apsp(W, inf=INF_I32, saturate=True):
                 out[s][t] = inf if b >= inf else int(b)
             else:
                 out[s][t] = b
+    return out
+
+
+def brute_last_hops(W, inf=INF_I32):
+    """For every (i, j) the set of last vertices before j over all shortest
+    simple i -> j paths (empty when unreachable or i == j), by enumeration."""
+    n = len(W)
+    D = brute_apsp(W, inf)
+    out = [[set() for _ in range(n)] for _ in range(n)]
+    for s in range(n):
+        def dfs(u, dist, seen):
+            for v in range(n):
+                if v in seen or W[u][v] >= inf:
+                    continue
+                nd = dist + W[u][v]
+                if nd == D[s][v] and nd < inf:
+                    out[s][v].add(u)
+                if nd <= D[s][v]:
+                    dfs(v, nd, seen | {v})
+        dfs(s, 0, {s})
     return out
 
 

@@ -306,3 +306,29 @@ int64_t oracle_certificate_i32(int64_t n, const int32_t *W, int64_t ldw,
     }
     return bad;
 }
+
+/* ------------------------------------------------------------------------
+ * Last-hop predecessors (Sec. 2: pred[i][j] is the vertex before j on the
+ * current i -> j path; Sec. 3.1 obtains it with an argmin over the
+ * intermediate index).  Written out from that definition: for i != j,
+ *   P[i][j] = the smallest v != j minimising D[i][v] (+) W[v][j]
+ * provided that minimum is below INF; otherwise (i == j, or j unreachable)
+ * P[i][j] = -1.  With D = APSP(W) and positive costs, W[v][j] is the last
+ * edge of a shortest i -> j path exactly when D[i][v] + W[v][j] = D[i][j].
+ * ---------------------------------------------------------------------- */
+void oracle_predecessors_i32(int64_t n, const int32_t *D, int64_t ldd, const int32_t *W, int64_t ldw,
+                             int32_t *P, int64_t ldp, int nthreads)
+{
+#pragma omp parallel for num_threads(nthreads > 0 ? nthreads : 1) schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t best = ORACLE_INF_I32;
+            int64_t arg = -1;
+            for (int64_t v = 0; v < n; ++v) {
+                if (v == j) continue;
+                int64_t t = sat_add_i32(D[i * ldd + v], W[v * ldw + j]);
+                if (t < best) { best = t; arg = v; }
+            }
+            P[i * ldp + j] = (i == j || best >= ORACLE_INF_I32) ? -1 : (int32_t)arg;
+        }
+}

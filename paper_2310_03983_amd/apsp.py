@@ -32,7 +32,7 @@ EXPORTS = [
     "apsp_solve", "apsp_batched", "apsp_validate", "apsp_profile_enable", "apsp_profile_read",
     "apsp_candidate_count", "apsp_candidate", "apsp_costmodel_init", "apsp_costmodel_set_norm",
     "apsp_costmodel_set_params", "apsp_costmodel_get_params", "apsp_costmodel_train", "apsp_costmodel_grad",
-    "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan",
+    "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
 ]
 
 KERNEL_MINPLUS_128, KERNEL_MINPLUS_64, KERNEL_CLOSURE, KERNEL_OTHER = 0, 1, 2, 3
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
                 getattr(L, name).argtypes = [vp, i32, i64, vp, i64, P(Opts), vp]
             L.apsp_batched.argtypes = [vp, i32, i32, vp, vp, vp, P(i32), P(Opts), vp]
             L.apsp_validate.argtypes = [vp, i32, i64, vp, i64, vp, P(i64)]
+            L.apsp_predecessors.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp]
             L.apsp_profile_enable.argtypes = [vp, i32]
             L.apsp_profile_read.argtypes = [vp, i32, P(KernelStats)]
             f32p = P(ctypes.c_float)
@@ -226,6 +227,45 @@ def apsp_square(D, opts=None, stream=None, **kw):
 def apsp_solve(D, opts=None, stream=None, **kw):
     """Planner-selected algorithm; D is overwritten."""
     return _square_call("apsp_solve", D, opts, stream, kw)
+
+
+def apsp_predecessors(D, W, P=None, stream=None):
+    """Last-hop predecessor matrix (int32 device tensor) of distances D for
+    costs W (Sec. 2); allocates P when it is not given."""
+    dt = _dtype(D)
+    if W.dtype != D.dtype:
+        raise TypeError("D and W must share a dtype")
+    pd, ldd = _matrix(D, "D")
+    pw, ldw = _matrix(W, "W")
+    n = D.shape[0]
+    if tuple(D.shape) != (n, n) or tuple(W.shape) != (n, n):
+        raise ValueError("D and W must be n x n")
+    if P is None:
+        P = torch.empty((n, n), dtype=torch.int32, device=D.device)
+    if P.dtype != torch.int32:
+        raise TypeError("P must be int32")
+    pp, ldp = _matrix(P, "P")
+    _check(lib().apsp_predecessors(context(D.device.index), dt, n, pd, ldd, pw, ldw, pp, ldp, _stream(D, stream)))
+    return P
+
+
+def reconstruct_path(P_row, i: int, j: int) -> list[int]:
+    """Vertices of the i -> j path encoded by row i of a predecessor matrix
+    (host array); [] when j is unreachable."""
+    if i == j:
+        return [i]
+    if P_row[j] < 0:
+        return []
+    path = [j]
+    v = j
+    for _ in range(len(P_row)):
+        v = int(P_row[v])
+        if v < 0:
+            raise ValueError("broken predecessor chain")
+        path.append(v)
+        if v == i:
+            return path[::-1]
+    raise ValueError("predecessor chain does not reach the source")
 
 
 def apsp_validate(D, stream=None) -> int:

@@ -589,6 +589,29 @@ apsp_status_t apsp_solve(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, i
     }
 }
 
+apsp_status_t apsp_predecessors(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
+                                const void* W, int64_t ldw, int32_t* P, int64_t ldp, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd)) || (rc = check_square(n, W, ldw)) ||
+        (rc = check_square(n, P, ldp)))
+        return rc;
+    if (n > INT32_MAX / 2) return fail(APSP_E_ARG, "n too large");
+    const size_t pb = span_bytes(n, n, ldp);
+    if (n > 0 && (overlaps(P, pb, D, span_bytes(n, n, ldd)) || overlaps(P, pb, W, span_bytes(n, n, ldw))))
+        return fail(APSP_E_ARG, "P overlaps D or W");
+    if ((rc = check_ctx(ctx))) return rc;
+    if (n == 0) return APSP_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    const double terms = (double)n * n * n;
+    return timed(ctx, APSP_KERNEL_OTHER, terms, 12.0 * n * n, st, [&]() -> apsp_status_t {
+        HIP_TRY(apsp::launch_predecessors((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, st),
+                "predecessor launch");
+        return APSP_OK;
+    });
+}
+
 apsp_status_t apsp_validate(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
                             void* stream, int64_t* h_violations)
 {

@@ -84,6 +84,10 @@ int batched_resident_per_cu(DType dt);
 const void* batched_kernel(DType dt);
 int batched_max_n();
 
+// ---- last-hop predecessors (pred.hip)
+hipError_t launch_predecessors(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
+                               int64_t ldp, int32_t n, hipStream_t st);
+
 // ---- cost-model MLP (mlp.hip)
 constexpr int kMlpIn = 4;
 constexpr int kMlpHidden = 64;

@@ -133,3 +133,26 @@ def test_candidate_table(native):
     assert algos == {1, 2, 3}
     with pytest.raises(native.ApspError):
         native.apsp_candidate(n)
+
+
+def test_predecessors_argument_errors(native):
+    L = native.lib()
+    D, W, P = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    f = L.apsp_predecessors
+    assert f(None, 0, 4, D, 4, W, 4, P, 3, None) == native.APSP_E_ARG
+    assert "ld" in native.last_error()
+    assert f(None, 0, 4, D, 4, W, 4, ctypes.c_void_p(0x100010), 4, None) == native.APSP_E_ARG
+    assert "overlap" in native.last_error()
+    assert f(None, 0, 4, D, 4, W, 4, P, 4, None) == native.APSP_E_ARG
+    assert "context" in native.last_error()
+
+
+def test_reconstruct_path_host_logic(native):
+    import numpy as np
+    row = np.array([-1, 0, 1, 1, -1], dtype=np.int32)   # 0->1->2, 0->1->3, 4 unreachable
+    assert native.reconstruct_path(row, 0, 2) == [0, 1, 2]
+    assert native.reconstruct_path(row, 0, 3) == [0, 1, 3]
+    assert native.reconstruct_path(row, 0, 4) == []
+    assert native.reconstruct_path(row, 0, 0) == [0]
+    with pytest.raises(ValueError):
+        native.reconstruct_path(np.array([-1, 2, 1], dtype=np.int32), 0, 2)

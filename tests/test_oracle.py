@@ -331,3 +331,43 @@ def test_oracle_fw_passes_pins(oracle):
 @pytest.mark.parametrize("kind", ["transposed", "k_innermost", "off_by_one", "no_saturation", "dropped_min"])
 def test_planted_fw_mistakes_are_caught(kind):
     assert not _fw_pins_pass(lambda W: _fw_mutant(W, kind))
+
+
+# ---------------------------------------------------------------------------
+# last-hop predecessors (Sec. 2 pred[i][j]; Sec. 3.1 argmin)
+# ---------------------------------------------------------------------------
+
+def test_predecessors_vs_bruteforce(oracle):
+    rng = np.random.default_rng(51)
+    for trial in range(60):
+        n = int(rng.integers(1, 8))
+        W = rand_graph(rng, n, 0.5, 1, 6)            # small costs: many ties
+        D = oracle.fw_i32(W)
+        P = oracle.predecessors_i32(D, W, threads=1)
+        hops = oracle.brute_last_hops(W.tolist())
+        for i in range(n):
+            for j in range(n):
+                want = min(hops[i][j]) if hops[i][j] else -1
+                assert P[i, j] == want, (trial, i, j, P[i, j], hops[i][j])
+
+
+def test_predecessor_walks_have_the_shortest_length(oracle):
+    rng = np.random.default_rng(52)
+    n = 70
+    W = rand_graph(rng, n, 0.05, 1, 100)
+    D = oracle.fw_i32(W)
+    P = oracle.predecessors_i32(D, W)
+    for i in range(n):
+        for j in range(n):
+            w = oracle.walk_weight(W, P, i, j)
+            if i != j and D[i, j] >= INF:
+                assert w is None
+            else:
+                assert w == D[i, j]
+    # a planted mistake (predecessors of the transposed problem) breaks a walk
+    bad = oracle.predecessors_i32(D.T.copy(), W.T.copy())
+    with pytest.raises(AssertionError):
+        for i in range(n):
+            for j in range(n):
+                w = oracle.walk_weight(W, bad, i, j)
+                assert w is None or w == D[i, j]
