@@ -75,6 +75,7 @@ typedef int32_t apsp_dtype_t;
 #define APSP_FLAG_NO_SPLITK        1  /* never split the reduction dimension */
 #define APSP_FLAG_BATCH_NO_GRAPH   2  /* apsp_batched: launch directly, no HIP graph */
 #define APSP_FLAG_BATCH_PER_GRAPH  4  /* apsp_batched: one launch per graph */
+#define APSP_FLAG_NO_LOOKAHEAD     8  /* blocked FW: strictly sequential rounds on the caller's stream */
 
 typedef struct apsp_opts {
     int32_t algo;      /* APSP_ALGO_*; only apsp_solve and apsp_batched read it */
@@ -132,6 +133,10 @@ apsp_status_t apsp_closure(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  * Eq. 1): for each round of width b, close the diagonal tile, update its row
  * and column panels, then every remaining tile with one min-plus product.
  * D (n x n, ldd >= n) is overwritten with distances.  opts may be NULL.
+ * By default round r+1's pivot closure and panel updates run on a second
+ * stream of the context, overlapped with the rest of round r's remainder
+ * update (APSP_FLAG_NO_LOOKAHEAD keeps everything on `stream`); the call
+ * still returns with all work ordered before later work on `stream`.
  */
 apsp_status_t apsp_fw(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                       void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);

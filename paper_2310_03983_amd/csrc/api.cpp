@@ -29,6 +29,9 @@ struct apsp_ctx {
     void* d_plan = nullptr;         // batched plan table (grown on demand)
     size_t plan_bytes = 0;
     hipStream_t capture = nullptr;  // private stream used only for graph capture
+    hipStream_t side = nullptr;     // second stream of the FW look-ahead
+    hipEvent_t ev_a = nullptr;      // look-ahead: band r+1 current
+    hipEvent_t ev_p = nullptr;      // look-ahead: pivot r+1 and panels done
     // cached batched plan: queue order on the device and the captured launch
     uint64_t bkey = 0;
     int32_t bcount = 0;
@@ -186,6 +189,7 @@ struct Plan {
     int closure;    // 1 k-loop, 2 squaring
     int cutover;    // R-Kleene -> FW below this size
     bool splitk;
+    bool lookahead; // FW: overlap the next pivot and panels with the remainder
 };
 
 Plan resolve(const apsp_opts_t* o)
@@ -196,6 +200,7 @@ Plan resolve(const apsp_opts_t* o)
     p.closure = o->closure ? o->closure : APSP_CLOSURE_KLOOP;
     p.cutover = o->cutover;
     p.splitk = !(o->flags & APSP_FLAG_NO_SPLITK);
+    p.lookahead = !(o->flags & APSP_FLAG_NO_LOOKAHEAD);
     return p;
 }
 
@@ -278,41 +283,106 @@ apsp_status_t closure(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int
 // ---------------------------------------------------------------------------
 // Blocked Floyd-Warshall on the window [off, off+n) x [off, off+n)
 // ---------------------------------------------------------------------------
+// phases 1 and 2 of round (k0, bk): close the pivot tile, then the row panel
+// R_KJ <- X* (min,+) R_KJ and the column panel C_IK <- C_IK (min,+) X*
+apsp_status_t fw_pivot_panels(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
+                              int64_t k0, int64_t bk, const Plan& pl, hipStream_t st)
+{
+    apsp_status_t rc = closure(ctx, dt, D, ld, off + k0, bk, pl.closure, st);
+    if (rc || bk == n) return rc;
+    const int t_p2 = apsp::TILE_64;                 // panels are thin: small tiles
+    const apsp::TileShape s2 = apsp::tile_shape(t_p2);
+    apsp::GemmGroup g2{};
+    g2.count = 2;
+    g2.p[0] = make_problem(dt, D, ld, off + k0, off + k0, off + k0, off, off + k0, off, bk, n, bk);
+    g2.p[0].skip_n0 = (int32_t)(k0 / s2.nt);
+    g2.p[0].skip_nc = (int32_t)((bk + s2.nt - 1) / s2.nt);
+    g2.p[1] = make_problem(dt, D, ld, off, off + k0, off + k0, off + k0, off, off + k0, n, bk, bk);
+    g2.p[1].skip_m0 = (int32_t)(k0 / s2.mt);
+    g2.p[1].skip_mc = (int32_t)((bk + s2.mt - 1) / s2.mt);
+    return run_group(ctx, dt, g2, pl, t_p2, st);
+}
+
+// Remainder update D_IJ <- min(D_IJ, C_IK (min,+) R_KJ) of round (k0, bk) for
+// the tiles whose row and column both lie outside the band [x0, x0 + xw)
+// (x0 tile-aligned; the band covers the pivot band and possibly the next one).
+apsp::GemmProblem remainder(apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n, int64_t k0, int64_t bk,
+                            int64_t x0, int64_t xw, const apsp::TileShape& ts)
+{
+    apsp::GemmProblem p = make_problem(dt, D, ld, off, off + k0, off + k0, off, off, off, n, n, bk);
+    p.skip_m0 = (int32_t)(x0 / ts.mt);
+    p.skip_mc = (int32_t)((xw + ts.mt - 1) / ts.mt);
+    p.skip_n0 = (int32_t)(x0 / ts.nt);
+    p.skip_nc = (int32_t)((xw + ts.nt - 1) / ts.nt);
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Floyd-Warshall on the window [off, off+n) x [off, off+n)
+//
+// Sequential order per round: pivot closure, panels, remainder.  With
+// look-ahead (default) the remainder of round r is split: first the tiles
+// of band r+1 (its row and its column), then -- on the caller's stream -- all
+// other tiles, while a second stream closes pivot r+1 and updates its panels
+// as soon as band r+1 is current.  The second stream touches only band r+1,
+// which the rest of round r neither reads nor writes; two events order the
+// streams.  The latency-bound closure and thin panel products then run under
+// the bulk remainder product instead of between rounds.
+// ---------------------------------------------------------------------------
 apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
                         const Plan& pl, hipStream_t st)
 {
     const int64_t b = pl.block;
-    const int t_p2 = apsp::TILE_64;                 // panels are thin: small tiles
-    // the excluded pivot band must be whole tiles: 64-wide rounds use 64-tiles
+    // the excluded bands must be whole tiles: 64-wide rounds use 64-tiles
     const int t_p3 = (b < 128) ? (int)apsp::TILE_64 : pick_tile(pl, n, n);
-    const apsp::TileShape s2 = apsp::tile_shape(t_p2), s3 = apsp::tile_shape(t_p3);
-    for (int64_t k0 = 0; k0 < n; k0 += b) {
-        const int64_t bk = std::min(b, n - k0);
-        // phase 1: close the pivot tile
-        apsp_status_t rc = closure(ctx, dt, D, ld, off + k0, bk, pl.closure, st);
-        if (rc) return rc;
+    const apsp::TileShape s3 = apsp::tile_shape(t_p3), s64 = apsp::tile_shape(apsp::TILE_64);
+    const int64_t rounds = (n + b - 1) / b;
+    const bool ahead = pl.lookahead && rounds >= 3 && ctx->side && ctx->ev_a && ctx->ev_p;
+    apsp_status_t rc = fw_pivot_panels(ctx, dt, D, ld, off, n, 0, std::min(b, n), pl, st);
+    if (rc) return rc;
+    for (int64_t r = 0; r < rounds; ++r) {
+        const int64_t k0 = r * b, bk = std::min(b, n - k0);
         if (bk == n) break;
-        // phase 2: row panel R_KJ <- X* (min,+) R_KJ and column panel C_IK <- C_IK (min,+) X*
-        apsp::GemmGroup g2{};
-        g2.count = 2;
-        g2.p[0] = make_problem(dt, D, ld, off + k0, off + k0, off + k0, off, off + k0, off, bk, n, bk);
-        g2.p[0].skip_n0 = (int32_t)(k0 / s2.nt);
-        g2.p[0].skip_nc = (int32_t)((bk + s2.nt - 1) / s2.nt);
-        g2.p[1] = make_problem(dt, D, ld, off, off + k0, off + k0, off + k0, off, off + k0, n, bk, bk);
-        g2.p[1].skip_m0 = (int32_t)(k0 / s2.mt);
-        g2.p[1].skip_mc = (int32_t)((bk + s2.mt - 1) / s2.mt);
-        rc = run_group(ctx, dt, g2, pl, t_p2, st);
+        if (!ahead || r + 1 == rounds) {
+            if (r > 0 && !ahead) {
+                rc = fw_pivot_panels(ctx, dt, D, ld, off, n, k0, bk, pl, st);
+                if (rc) return rc;
+            }
+            apsp::GemmGroup g3{};
+            g3.count = 1;
+            g3.p[0] = remainder(dt, D, ld, off, n, k0, bk, k0, bk, s3);
+            rc = run_group(ctx, dt, g3, pl, t_p3, st);
+            if (rc) return rc;
+            continue;
+        }
+        const int64_t k1 = k0 + b, bk1 = std::min(b, n - k1);
+        // (a) band r+1: its row (all columns outside band r) and its column
+        //     (rows outside bands r and r+1), thin products on 64-tiles
+        apsp::GemmGroup ga{};
+        ga.count = 2;
+        ga.p[0] = make_problem(dt, D, ld, off + k1, off + k0, off + k0, off, off + k1, off, bk1, n, bk);
+        ga.p[0].skip_n0 = (int32_t)(k0 / s64.nt);
+        ga.p[0].skip_nc = (int32_t)(bk / s64.nt);
+        ga.p[1] = make_problem(dt, D, ld, off, off + k0, off + k0, off + k1, off, off + k1, n, bk1, bk);
+        ga.p[1].skip_m0 = (int32_t)(k0 / s64.mt);
+        ga.p[1].skip_mc = (int32_t)((bk + bk1 + s64.mt - 1) / s64.mt);
+        rc = run_group(ctx, dt, ga, pl, apsp::TILE_64, st);
         if (rc) return rc;
-        // phase 3: D_IJ <- min(D_IJ, C_IK (min,+) R_KJ) for I, J outside the pivot band
-        apsp::GemmGroup g3{};
-        g3.count = 1;
-        g3.p[0] = make_problem(dt, D, ld, off, off + k0, off + k0, off, off, off, n, n, bk);
-        g3.p[0].skip_m0 = (int32_t)(k0 / s3.mt);
-        g3.p[0].skip_mc = (int32_t)((bk + s3.mt - 1) / s3.mt);
-        g3.p[0].skip_n0 = (int32_t)(k0 / s3.nt);
-        g3.p[0].skip_nc = (int32_t)((bk + s3.nt - 1) / s3.nt);
-        rc = run_group(ctx, dt, g3, pl, t_p3, st);
+        HIP_TRY(hipEventRecord(ctx->ev_a, st), "look-ahead event");
+        // (b) second stream: pivot r+1 and its panels
+        HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_a, 0), "look-ahead wait");
+        rc = fw_pivot_panels(ctx, dt, D, ld, off, n, k1, bk1, pl, ctx->side);
         if (rc) return rc;
+        HIP_TRY(hipEventRecord(ctx->ev_p, ctx->side), "look-ahead event");
+        // (c) caller's stream: every tile outside bands r and r+1
+        apsp::GemmGroup gb{};
+        gb.count = 1;
+        gb.p[0] = remainder(dt, D, ld, off, n, k0, bk, k0, bk + bk1, s3);
+        if (gb.p[0].M > 0) {
+            rc = run_group(ctx, dt, gb, pl, t_p3, st);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipStreamWaitEvent(st, ctx->ev_p, 0), "look-ahead join");
     }
     return APSP_OK;
 }
@@ -461,10 +531,23 @@ apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
         delete c;
         return fail(APSP_E_HIP, "capture stream creation failed");
     }
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_p, hipEventDisableTiming) != hipSuccess) {
+        if (c->side) hipStreamDestroy(c->side);
+        if (c->ev_a) hipEventDestroy(c->ev_a);
+        if (c->ev_p) hipEventDestroy(c->ev_p);
+        hipStreamDestroy(c->capture);
+        delete c;
+        return fail(APSP_E_HIP, "look-ahead stream creation failed");
+    }
     c->scratch_bytes = 4096;
     hipError_t e = hipMalloc(&c->d_scratch, c->scratch_bytes);
     if (e != hipSuccess) {
         hipStreamDestroy(c->capture);
+        hipStreamDestroy(c->side);
+        hipEventDestroy(c->ev_a);
+        hipEventDestroy(c->ev_p);
         delete c;
         return fail(APSP_E_NOMEM, "scratch allocation: %s", hipGetErrorString(e));
     }
@@ -485,6 +568,9 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
     if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
     if (ctx->capture) hipStreamDestroy(ctx->capture);
+    if (ctx->side) hipStreamDestroy(ctx->side);
+    if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
+    if (ctx->ev_p) hipEventDestroy(ctx->ev_p);
     ctx->magic = 0;
     delete ctx;
     return APSP_OK;

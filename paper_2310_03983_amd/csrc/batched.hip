@@ -21,7 +21,7 @@ namespace {
 using dev::kMaxS;
 
 constexpr int kB = 128;                                  // round width
-constexpr int kLdsClose = kMaxS * (kMaxS + 2) * 4;       // closure block
+constexpr int kLdsClose = dev::kCloseLdsWords * 4;       // closure band buffers
 constexpr int kLdsTile = 2 * 2 * (16 / 2) * (kB + 2) * 8; // A and B staging (pairs)
 constexpr int kLds = kLdsClose > kLdsTile ? kLdsClose : kLdsTile;
 

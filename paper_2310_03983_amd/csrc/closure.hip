@@ -25,8 +25,8 @@ using CF32 = dev::SemF32;
 template <class S>
 __global__ __launch_bounds__(256) void k_closure_kloop(typename S::T* __restrict__ D, int64_t ld, int s)
 {
-    __shared__ __attribute__((aligned(16))) typename S::T X[kMaxS * (kMaxS + 2)];
-    dev::close_block<S>(D, ld, s, X);
+    __shared__ __attribute__((aligned(16))) typename S::T lds[dev::kCloseLdsWords];
+    dev::close_block<S>(D, ld, s, lds);
 }
 
 template <class S>

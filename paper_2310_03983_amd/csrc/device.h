@@ -298,25 +298,36 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
 
 // Blocked form of the Eq. 1 k-loop for one block of s <= 128, in one
 // workgroup of 256 lanes.  Lane (ty, tx) owns the 8 x 8 elements at rows
-// ty + 16*i and columns tx + 16*j, kept in registers; LDS mirrors the whole
-// block so that other lanes can read pivot rows and columns.  The k range is
-// cut into four 32-wide pivot bands P.  With this interleaving, band r is
-// exactly register rows/columns {2r, 2r+1} of every lane, so each round has
-// the same shape on every lane:
-//   1. pivot block P x P: the Eq. 1 k-loop over k in P, in place in LDS (row
-//      k and column k do not change during step k), one barrier per step;
-//   2. panels: rows P x other columns <- P* (min,+) panel and other rows x
-//      columns P <- panel (min,+) P*, computed from the pre-update panels,
-//      then written back;
-//   3. remainder: other x other <- min(., column panel (min,+) row panel).
-// Phases 2 and 3 fold two k at a time with the packed 64-bit add / min3 pair
-// used by the product kernel.  Each element is written only by its owner.
+// ty + 16*i and columns tx + 16*j and keeps them in registers for the whole
+// call.  The k range is cut into four 32-wide bands; with this interleaving,
+// band r is exactly register rows/columns {2r, 2r+1} of every lane, so every
+// round has the same shape on every lane.  Only the current band is shared
+// through LDS: its 32 rows (R) and its 32 columns (Cc), 34 KB in all.
+//   0. owners publish band r's rows and columns;
+//   1. pivot block (band x band): the Eq. 1 k-loop over k in the band, in
+//      place in R and Cc (row k and column k do not change during step k),
+//      one barrier per step;
+//   2. panels: band rows x other columns <- P* (min,+) row panel and other
+//      rows x band columns <- column panel (min,+) P*, from the pre-update
+//      panels, then written back to R / Cc;
+//   3. remainder: other x other <- min(., column panel (min,+) row panel),
+//      registers only.
+// Phases 2 and 3 fold two k at a time with the packed add / min3 pair of the
+// product kernel.  Entries outside the block are INF, so steps past its
+// edge change nothing.
+constexpr int kBand = 32;
+constexpr int kLdR = kMaxS + 2;          // R: kBand rows of kMaxS (+2: even, staggered banks)
+constexpr int kLdC = kBand + 2;          // Cc: kMaxS rows of kBand (+2)
+constexpr int kCloseLdsWords = kBand * kLdR + kMaxS * kLdC;
+
 template <class S>
 __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64_t ld, int s,
-                                            typename S::T* X)
+                                            typename S::T* lds)
 {
     using T = typename S::T;
-    constexpr int LDX = kMaxS + 2;          // even: 8-byte aligned row pairs
+    using P = typename S::P;
+    T* R = lds;                       // R[kk * kLdR + col]  = X[p0 + kk][col]
+    T* Cc = lds + kBand * kLdR;       // Cc[row * kLdC + kk] = X[row][p0 + kk]
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
 
@@ -328,41 +339,51 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
         for (int j = 0; j < 8; ++j) {
             const int c = tx + 16 * j;
             x[i][j] = (r < s && c < s) ? D[(int64_t)r * ld + c] : S::inf();
-            X[r * LDX + c] = x[i][j];
         }
     }
-    __syncthreads();
 
-    const int rounds = (s + 31) / 32;
+    const int rounds = (s + kBand - 1) / kBand;
     // fully unrolled so that the band's register rows/columns are constants
 #pragma unroll
-    for (int rd = 0; rd < kMaxS / 32; ++rd) {
+    for (int rd = 0; rd < kMaxS / kBand; ++rd) {
         if (rd >= rounds) break;
-        const int p0 = 32 * rd;
-        const int pc = min(32, s - p0);
+        const int p0 = kBand * rd;
+        const int pc = min(kBand, s - p0);
         const int i0 = 2 * rd;               // register rows/cols of band rd
-        // ---- 1. pivot block
-        for (int k = p0; k < p0 + pc; ++k) {
+        // ---- 0. publish band rows and columns
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) R[(ty + 16 * a) * kLdR + tx + 16 * j] = x[i0 + a][j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) Cc[(ty + 16 * i) * kLdC + tx + 16 * b] = x[i][i0 + b];
+        __syncthreads();
+        // ---- 1. pivot block, in place in R (band rows hold the whole pivot);
+        //      Cc's copy of the pivot is refreshed once afterwards
+        for (int kk = 0; kk < pc; ++kk) {
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                const T cv = X[(ty + 16 * (i0 + a)) * LDX + k];
+                const T cv = R[(ty + 16 * a) * kLdR + p0 + kk];
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    const T rv = X[k * LDX + tx + 16 * (i0 + b)];
+                    const T rv = R[kk * kLdR + tx + 16 * (i0 + b)];
                     x[i0 + a][i0 + b] = S::relax(x[i0 + a][i0 + b], cv, rv);
                 }
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    X[(ty + 16 * (i0 + a)) * LDX + tx + 16 * (i0 + b)] = x[i0 + a][i0 + b];
+                for (int b = 0; b < 2; ++b) R[(ty + 16 * a) * kLdR + tx + 16 * (i0 + b)] = x[i0 + a][i0 + b];
             __syncthreads();
         }
-        // ---- 2. panels (from the pre-update panel values).  Every band is
-        // walked as 16 full pair-steps: entries outside the block are INF in
-        // LDS, so steps past the block edge change nothing.
-        using P = typename S::P;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) Cc[(ty + 16 * (i0 + a)) * kLdC + tx + 16 * b] = x[i0 + a][i0 + b];
+        __syncthreads();
+        // ---- 2. panels (from the pre-update panel values)
         T nr[2][8], nc[8][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -373,15 +394,13 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
 #pragma unroll
             for (int b = 0; b < 2; ++b) nc[i][b] = x[i][i0 + b];
 #pragma unroll 2
-        for (int kk = 0; kk < 32; kk += 2) {
-            const int k = p0 + kk;
+        for (int kk = 0; kk < kBand; kk += 2) {
             P pa[8], pb[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                pa[i] = *reinterpret_cast<const P*>(&X[(ty + 16 * i) * LDX + k]);
+            for (int i = 0; i < 8; ++i) pa[i] = *reinterpret_cast<const P*>(&Cc[(ty + 16 * i) * kLdC + kk]);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                pb[j] = S::pair(X[k * LDX + tx + 16 * j], X[(k + 1) * LDX + tx + 16 * j]);
+                pb[j] = S::pair(R[kk * kLdR + tx + 16 * j], R[(kk + 1) * kLdR + tx + 16 * j]);
             // row panel: P*[row][k..k+1] + R[k..k+1][col]
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -400,7 +419,7 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
             for (int j = 0; j < 8; ++j) {
                 if (j == i0 || j == i0 + 1) continue;
                 x[i0 + a][j] = nr[a][j];
-                X[(ty + 16 * (i0 + a)) * LDX + tx + 16 * j] = nr[a][j];
+                R[(ty + 16 * a) * kLdR + tx + 16 * j] = nr[a][j];
             }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -408,21 +427,19 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 x[i][i0 + b] = nc[i][b];
-                X[(ty + 16 * i) * LDX + tx + 16 * (i0 + b)] = nc[i][b];
+                Cc[(ty + 16 * i) * kLdC + tx + 16 * b] = nc[i][b];
             }
         }
         __syncthreads();
-        // ---- 3. remainder: other rows x other columns
+        // ---- 3. remainder: other rows x other columns (registers only)
 #pragma unroll 2
-        for (int kk = 0; kk < 32; kk += 2) {
-            const int k = p0 + kk;
+        for (int kk = 0; kk < kBand; kk += 2) {
             P pa[8], pb[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                pa[i] = *reinterpret_cast<const P*>(&X[(ty + 16 * i) * LDX + k]);
+            for (int i = 0; i < 8; ++i) pa[i] = *reinterpret_cast<const P*>(&Cc[(ty + 16 * i) * kLdC + kk]);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                pb[j] = S::pair(X[k * LDX + tx + 16 * j], X[(k + 1) * LDX + tx + 16 * j]);
+                pb[j] = S::pair(R[kk * kLdR + tx + 16 * j], R[(kk + 1) * kLdR + tx + 16 * j]);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 if (i == i0 || i == i0 + 1) continue;
@@ -433,16 +450,7 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
                 }
             }
         }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            if (i == i0 || i == i0 + 1) continue;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (j == i0 || j == i0 + 1) continue;
-                X[(ty + 16 * i) * LDX + tx + 16 * j] = x[i][j];
-            }
-        }
-        __syncthreads();
+        __syncthreads();                     // R / Cc are republished next round
     }
 
 #pragma unroll
