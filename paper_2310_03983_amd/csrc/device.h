@@ -304,9 +304,9 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
 // round has the same shape on every lane.  Only the current band is shared
 // through LDS: its 32 rows (R) and its 32 columns (Cc), 34 KB in all.
 //   0. owners publish band r's rows and columns;
-//   1. pivot block (band x band): the Eq. 1 k-loop over k in the band, in
-//      place in R and Cc (row k and column k do not change during step k),
-//      one barrier per step;
+//   1. pivot block (band x band): closed by min-plus squaring to a fixpoint
+//      (each pass doubles the hop reach; the closure equals the Eq. 1
+//      k-loop's), a few parallel passes instead of 32 barrier steps;
 //   2. panels: band rows x other columns <- P* (min,+) row panel and other
 //      rows x band columns <- column panel (min,+) P*, from the pre-update
 //      panels, then written back to R / Cc;
@@ -348,7 +348,6 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
     for (int rd = 0; rd < kMaxS / kBand; ++rd) {
         if (rd >= rounds) break;
         const int p0 = kBand * rd;
-        const int pc = min(kBand, s - p0);
         const int i0 = 2 * rd;               // register rows/cols of band rd
         // ---- 0. publish band rows and columns
 #pragma unroll
@@ -360,23 +359,44 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
 #pragma unroll
             for (int b = 0; b < 2; ++b) Cc[(ty + 16 * i) * kLdC + tx + 16 * b] = x[i][i0 + b];
         __syncthreads();
-        // ---- 1. pivot block, in place in R (band rows hold the whole pivot);
-        //      Cc's copy of the pivot is refreshed once afterwards
-        for (int kk = 0; kk < pc; ++kk) {
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const T cv = R[(ty + 16 * a) * kLdR + p0 + kk];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const T rv = R[kk * kLdR + tx + 16 * (i0 + b)];
-                    x[i0 + a][i0 + b] = S::relax(x[i0 + a][i0 + b], cv, rv);
-                }
-            }
+        // ---- 1. pivot block: min-plus squaring to a fixpoint (Sec. 3.2 at band
+        //      scale) on R, which holds the whole pivot in its band columns.
+        //      Each pass doubles the hop reach, so at most 6 passes change
+        //      anything for 32 vertices; a pass that changes nothing ends it.
+        //      Cc's copy of the pivot is refreshed afterwards.
+        for (int pass = 0; pass < 8; ++pass) {
+            T np[2][2];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) R[(ty + 16 * a) * kLdR + tx + 16 * (i0 + b)] = x[i0 + a][i0 + b];
-            __syncthreads();
+                for (int b = 0; b < 2; ++b) np[a][b] = x[i0 + a][i0 + b];
+#pragma unroll 4
+            for (int kk = 0; kk < kBand; kk += 2) {
+                P pa[2], pb[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) pa[a] = *reinterpret_cast<const P*>(&R[(ty + 16 * a) * kLdR + p0 + kk]);
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    pb[b] = S::pair(R[kk * kLdR + tx + 16 * (i0 + b)], R[(kk + 1) * kLdR + tx + 16 * (i0 + b)]);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) np[a][b] = S::fold(np[a][b], pa[a], pb[b]);
+            }
+            int changed = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) changed |= np[a][b] < x[i0 + a][i0 + b];
+            __syncthreads();                 // every read of this pass is done
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    x[i0 + a][i0 + b] = np[a][b];
+                    R[(ty + 16 * a) * kLdR + tx + 16 * (i0 + b)] = np[a][b];
+                }
+            if (!__syncthreads_or(changed)) break;
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
