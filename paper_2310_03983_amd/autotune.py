@@ -226,12 +226,12 @@ def predict(model, X):
 
 
 def size_rule(n, cands):
-    """Index of the candidate closest to what the library's size rule runs
-    (blocked FW up to n = 4096, R-Kleene with a FW cutover above)."""
+    """Index of the candidate the library's size rule runs (blocked FW up to
+    n = 4096, R-Kleene with a 4096 FW cutover above)."""
     if n <= 4096:
         want = {"algo": 1, "block": 128, "tile": 0, "closure": 1, "cutover": 0}
     else:
-        want = {"algo": 2, "block": 128, "tile": 0, "closure": 1, "cutover": 1024}
+        want = {"algo": 2, "block": 128, "tile": 0, "closure": 1, "cutover": 4096}
     for i, c in enumerate(cands):
         if c == want:
             return i

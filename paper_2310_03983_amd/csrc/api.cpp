@@ -470,10 +470,10 @@ struct Candidate {
     int32_t algo, block, tile, closure, cutover;
 };
 const Candidate kCandidates[] = {
-    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
+    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},        // size rule, n <= 4096
     {APSP_ALGO_FW, 64, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
     {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
-    {APSP_ALGO_RKLEENE, 64, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 4096},  // size rule, n > 4096
     {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 1024},
     {APSP_ALGO_RKLEENE, 128, APSP_TILE_64, APSP_CLOSURE_KLOOP, 0},
     {APSP_ALGO_SQUARE, 0, APSP_TILE_AUTO, APSP_CLOSURE_AUTO, 0},
