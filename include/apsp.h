@@ -76,6 +76,7 @@ typedef int32_t apsp_dtype_t;
 #define APSP_FLAG_BATCH_NO_GRAPH   2  /* apsp_batched: launch directly, no HIP graph */
 #define APSP_FLAG_BATCH_PER_GRAPH  4  /* apsp_batched: one launch per graph */
 #define APSP_FLAG_NO_LOOKAHEAD     8  /* blocked FW: strictly sequential rounds on the caller's stream */
+#define APSP_FLAG_BATCH_PERSISTENT 16 /* apsp_batched: one persistent kernel, one workgroup per graph */
 
 typedef struct apsp_opts {
     int32_t algo;      /* APSP_ALGO_*; only apsp_solve and apsp_batched read it */
@@ -186,19 +187,24 @@ apsp_status_t apsp_predecessors(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                                 int32_t *P, int64_t ldp, void *stream);
 
 /*
- * Many independent graphs in one launch.  `data` holds `count` square
+ * Many independent graphs, solved together.  `data` holds `count` square
  * row-major matrices back to back; d_offsets[g] (int64, device) is the
  * element offset of graph g and d_sizes[g] (int32, device) its n; h_sizes is
  * the same sizes on the host (used to plan, never dereferenced on device).
  * Every matrix is overwritten with its distances (Sec. 2, Eq. 1 per graph).
- * Workgroups of one persistent kernel take whole graphs, largest first, from
- * an atomic queue; the launch (counter reset + kernel) is captured once per
- * batch shape in a HIP graph and replayed, with the data pointers updated in
- * the instantiated graph.  n <= 1024 per graph (APSP_E_UNSUPPORTED beyond:
- * use apsp_solve).  Flags: APSP_FLAG_BATCH_NO_GRAPH launches directly;
- * APSP_FLAG_BATCH_PER_GRAPH issues one launch per graph (a baseline).
- * The context keeps the queue order in device memory it allocates on first
- * use; calls on one context must not overlap across streams.
+ * Default schedule (lock-step): all graphs advance one 128-wide blocked-FW
+ * round per three wide launches (pivot closures, panel tiles, remainder
+ * tiles of every graph), at most 3 * ceil(max n / 128) launches, captured
+ * once per batch shape in a HIP graph and replayed (the buffers of each call
+ * are written to a small device record first, so any buffers work).
+ * APSP_FLAG_BATCH_PERSISTENT: one persistent kernel whose workgroups take
+ * whole graphs, largest first, from an atomic queue (also graph-captured).
+ * APSP_FLAG_BATCH_NO_GRAPH launches directly; APSP_FLAG_BATCH_PER_GRAPH
+ * issues one launch per graph (a baseline).  n <= 1024 per graph
+ * (APSP_E_UNSUPPORTED beyond: use apsp_solve).  The context keeps the plan
+ * in device memory it allocates when a new batch shape arrives (that call
+ * synchronises `stream`); calls on one context must not overlap across
+ * streams.
  */
 apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
                            void *data, const int64_t *d_offsets, const int32_t *d_sizes,

@@ -23,7 +23,7 @@ INF_I32 = 1 << 30
 ALGO = {"auto": 0, "fw": 1, "rkleene": 2, "square": 3}
 CLOSURE = {"auto": 0, "kloop": 1, "square": 2}
 TILE = {"auto": 0, 128: 1, 64: 2}
-FLAG_NO_SPLITK, FLAG_BATCH_NO_GRAPH, FLAG_BATCH_PER_GRAPH, FLAG_NO_LOOKAHEAD = 1, 2, 4, 8
+FLAG_NO_SPLITK, FLAG_BATCH_NO_GRAPH, FLAG_BATCH_PER_GRAPH, FLAG_NO_LOOKAHEAD, FLAG_BATCH_PERSISTENT = 1, 2, 4, 8, 16
 
 # every symbol include/apsp.h declares
 EXPORTS = [
@@ -62,7 +62,7 @@ class KernelStats(ctypes.Structure):
 
 
 def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True,
-              batch_graph=True, batch_per_graph=False, lookahead=True) -> Opts:
+              batch_graph=True, batch_per_graph=False, lookahead=True, batch_persistent=False) -> Opts:
     o = Opts()
     o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
     o.block = int(block)
@@ -70,7 +70,8 @@ def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, spli
     o.closure = CLOSURE[closure] if isinstance(closure, str) else int(closure)
     o.cutover = int(cutover)
     o.flags = (0 if splitk else FLAG_NO_SPLITK) | (0 if batch_graph else FLAG_BATCH_NO_GRAPH) | \
-        (FLAG_BATCH_PER_GRAPH if batch_per_graph else 0) | (0 if lookahead else FLAG_NO_LOOKAHEAD)
+        (FLAG_BATCH_PER_GRAPH if batch_per_graph else 0) | (0 if lookahead else FLAG_NO_LOOKAHEAD) | \
+        (FLAG_BATCH_PERSISTENT if batch_persistent else 0)
     return o
 
 

@@ -42,6 +42,15 @@ struct apsp_ctx {
     hipGraphNode_t bnode = nullptr;
     hipKernelNodeParams bparams{};
     apsp::BatchArgs bargs{};
+    // lock-step batched schedule: work items and launch list, captured graph
+    std::vector<int4> litems;
+    struct Launch { int phase, offset, count; };
+    std::vector<Launch> llaunches;
+    int4* d_items = nullptr;
+    size_t items_bytes = 0;
+    apsp::BatchPtrs* d_bptrs = nullptr;
+    hipGraph_t lgraph = nullptr;
+    hipGraphExec_t lexec = nullptr;
     // cost model
     int32_t cm_K = 0;
     float* cm_params = nullptr;     // device: parameters, Adam moments, gradients
@@ -567,6 +576,10 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     free_costmodel(ctx);
     if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
     if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+    if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
+    if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
+    if (ctx->d_items) hipFree(ctx->d_items);
+    if (ctx->d_bptrs) hipFree(ctx->d_bptrs);
     if (ctx->capture) hipStreamDestroy(ctx->capture);
     if (ctx->side) hipStreamDestroy(ctx->side);
     if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
@@ -760,13 +773,66 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
             if (e != hipSuccess) return fail(APSP_E_NOMEM, "plan allocation: %s", hipGetErrorString(e));
             ctx->plan_bytes = need;
         }
+        // lock-step work items, graphs in largest-first order within each launch
+        const int B = apsp::batched_round_width();
+        std::vector<int4> items;
+        std::vector<apsp_ctx::Launch> launches;
+        int max_rounds = 0;
+        for (int32_t g = 0; g < count; ++g) max_rounds = std::max(max_rounds, (h_sizes[g] + B - 1) / B);
+        for (int r = 0; r < max_rounds; ++r) {
+            for (int phase = 0; phase < 3; ++phase) {
+                const int start = (int)items.size();
+                for (int32_t q = 0; q < count; ++q) {
+                    const int32_t g = order[q];
+                    const int nb = (h_sizes[g] + B - 1) / B;
+                    if (nb <= r || (phase > 0 && nb < 2)) continue;
+                    if (phase == 0) {
+                        items.push_back(make_int4(g, r, 0, 0));
+                    } else if (phase == 1) {
+                        for (int t = 0; t < nb; ++t)
+                            if (t != r) {
+                                items.push_back(make_int4(g, r, t, 0));
+                                items.push_back(make_int4(g, r, t, 1));
+                            }
+                    } else {
+                        for (int ti = 0; ti < nb; ++ti)
+                            for (int tj = 0; tj < nb; ++tj)
+                                if (ti != r && tj != r) items.push_back(make_int4(g, r, ti, tj));
+                    }
+                }
+                const int cnt = (int)items.size() - start;
+                if (cnt > 0) launches.push_back({phase, start, cnt});
+            }
+        }
+        const size_t ib = std::max<size_t>(items.size(), 1) * sizeof(int4);
+        if (ib > ctx->items_bytes || !ctx->d_bptrs) {
+            HIP_TRY(hipStreamSynchronize(st), "plan sync");
+            if (ctx->d_items) hipFree(ctx->d_items);
+            ctx->d_items = nullptr;
+            ctx->items_bytes = 0;
+            hipError_t e = hipMalloc(&ctx->d_items, ib);
+            if (e == hipSuccess && !ctx->d_bptrs) e = hipMalloc(&ctx->d_bptrs, sizeof(apsp::BatchPtrs));
+            if (e != hipSuccess) return fail(APSP_E_NOMEM, "batch plan allocation: %s", hipGetErrorString(e));
+            ctx->items_bytes = ib;
+        }
         ctx->border = std::move(order);
+        ctx->litems = std::move(items);
+        ctx->llaunches = std::move(launches);
         HIP_TRY(hipMemcpyAsync(ctx->d_plan, ctx->border.data(), need, hipMemcpyHostToDevice, st), "plan upload");
+        if (!ctx->litems.empty())
+            HIP_TRY(hipMemcpyAsync(ctx->d_items, ctx->litems.data(), ctx->litems.size() * sizeof(int4),
+                                   hipMemcpyHostToDevice, st),
+                    "plan upload");
+        HIP_TRY(hipStreamSynchronize(st), "plan upload sync");
         if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
         if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+        if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
+        if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
         ctx->bexec = nullptr;
         ctx->bgraph = nullptr;
         ctx->bnode = nullptr;
+        ctx->lexec = nullptr;
+        ctx->lgraph = nullptr;
         ctx->bkey = key;
         ctx->bcount = count;
         ctx->bdtype = dt;
@@ -782,6 +848,46 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
     const int grid = std::min<int>(count, ctx->num_cus * apsp::batched_resident_per_cu(kdt));
     const double terms = 0.0, bytes = 0.0;
 
+    if (!(o->flags & (APSP_FLAG_BATCH_PERSISTENT | APSP_FLAG_BATCH_PER_GRAPH))) {
+        // lock-step schedule: point the device record at this call's buffers,
+        // then run the launch list (captured once per batch shape)
+        auto enqueue = [&](hipStream_t s2) -> hipError_t {
+            for (const auto& L : ctx->llaunches) {
+                hipError_t e = apsp::launch_batch_phase(kdt, L.phase, ctx->d_bptrs, ctx->d_items + L.offset,
+                                                        L.count, s2);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
+            HIP_TRY(apsp::launch_batch_ptrs(ctx->d_bptrs, data, d_offsets, d_sizes, st), "batch pointer update");
+            if (o->flags & APSP_FLAG_BATCH_NO_GRAPH) {
+                HIP_TRY(enqueue(st), "lock-step launch");
+                return APSP_OK;
+            }
+            if (!ctx->lexec) {
+                HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+                hipError_t le = enqueue(ctx->capture);
+                hipGraph_t g = nullptr;
+                hipError_t ce = hipStreamEndCapture(ctx->capture, &g);
+                if (le != hipSuccess) {
+                    if (g) hipGraphDestroy(g);
+                    return hip_fail(le, "lock-step capture launch");
+                }
+                HIP_TRY(ce, "end capture");
+                hipGraphExec_t ex = nullptr;
+                hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                if (ie != hipSuccess) {
+                    hipGraphDestroy(g);
+                    return hip_fail(ie, "graph instantiate");
+                }
+                ctx->lgraph = g;
+                ctx->lexec = ex;
+            }
+            HIP_TRY(hipGraphLaunch(ctx->lexec, st), "graph launch");
+            return APSP_OK;
+        });
+    }
     if (o->flags & APSP_FLAG_BATCH_PER_GRAPH) {
         // baseline: one launch (of the same kernel) per graph
         for (int32_t q = 0; q < count; ++q) {

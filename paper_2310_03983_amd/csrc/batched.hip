@@ -115,6 +115,81 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lock-step schedule: every graph advances one 128-wide Floyd-Warshall round
+// per three wide launches -- (1) the pivot closures of all graphs, (2) all
+// their panel tiles, (3) all their remainder tiles -- so a graph's tiles are
+// spread over the whole device instead of one workgroup.  Work items are
+// (graph, round, a, b): closure (a = b = 0); panel tile a of the row (b = 0)
+// or column (b = 1) panel; remainder tile (a, b).  Graphs with n <= 128 are
+// finished by their round-0 closure.  Data pointers are read from a small
+// device record so that a captured launch sequence serves any buffers.
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void k_bclose(const BatchPtrs* __restrict__ bp, const int4* __restrict__ items)
+{
+    using T = typename S::T;
+    __shared__ __attribute__((aligned(16))) T lds[dev::kCloseLdsWords];
+    const int4 it = items[blockIdx.x];
+    const int n = bp->sizes[it.x];
+    T* D = static_cast<T*>(bp->data) + bp->offsets[it.x];
+    const int k0 = it.y * kB;
+    dev::close_block<S>(D + (int64_t)k0 * n + k0, n, min(kB, n - k0), lds);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_btile(const BatchPtrs* __restrict__ bp, const int4* __restrict__ items,
+                                               int phase)
+{
+    using T = typename S::T;
+    using P = typename S::P;
+    __shared__ P As[2][8][kB + 2];
+    __shared__ P Bs[2][8][kB + 2];
+    const int4 it = items[blockIdx.x];
+    const int n = bp->sizes[it.x];
+    T* D = static_cast<T*>(bp->data) + bp->offsets[it.x];
+    const int64_t ld = n;
+    const int k0 = it.y * kB, bk = min(kB, n - k0);
+    T* piv = D + (int64_t)k0 * ld + k0;
+    const T* A;
+    const T* B;
+    T* C;
+    int M, N;
+    if (phase == 1) {
+        const int o0 = it.z * kB, w = min(kB, n - o0);
+        if (it.w == 0) {            // row panel R_KJ <- X* (min,+) R_KJ
+            A = piv;
+            C = D + (int64_t)k0 * ld + o0;
+            B = C;
+            M = bk;
+            N = w;
+        } else {                    // column panel C_IK <- C_IK (min,+) X*
+            C = D + (int64_t)o0 * ld + k0;
+            A = C;
+            B = piv;
+            M = w;
+            N = bk;
+        }
+    } else {                        // remainder D_IJ <- min(D_IJ, C_IK (min,+) R_KJ)
+        const int r0 = it.z * kB, c0 = it.w * kB;
+        A = D + (int64_t)r0 * ld + k0;
+        B = D + (int64_t)k0 * ld + c0;
+        C = D + (int64_t)r0 * ld + c0;
+        M = min(kB, n - r0);
+        N = min(kB, n - c0);
+    }
+    dev::mp_tile<S, kB, kB, 16, 8, 8, true>(A, ld, B, ld, C, ld, M, N, 0, 0, 0, bk, false, nullptr, As, Bs);
+}
+
+__global__ void k_set_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, const int32_t* sizes)
+{
+    if (threadIdx.x == 0) {
+        bp->data = data;
+        bp->offsets = offsets;
+        bp->sizes = sizes;
+    }
+}
+
 }  // namespace
 
 const void* batched_kernel(DType dt)
@@ -136,6 +211,32 @@ hipError_t launch_batched(DType dt, const BatchArgs& a, int grid, hipStream_t st
         hipLaunchKernelGGL(k_batched<dev::SemF32>, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
+
+hipError_t launch_batch_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, const int32_t* sizes,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, st, bp, data, offsets, sizes);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const int4* items, int count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (phase == 0) {
+        if (dt == I32)
+            hipLaunchKernelGGL(k_bclose<dev::SemI32>, dim3(count), dim3(256), 0, st, bp, items);
+        else
+            hipLaunchKernelGGL(k_bclose<dev::SemF32>, dim3(count), dim3(256), 0, st, bp, items);
+    } else {
+        if (dt == I32)
+            hipLaunchKernelGGL(k_btile<dev::SemI32>, dim3(count), dim3(256), 0, st, bp, items, phase);
+        else
+            hipLaunchKernelGGL(k_btile<dev::SemF32>, dim3(count), dim3(256), 0, st, bp, items, phase);
+    }
+    return hipGetLastError();
+}
+
+int batched_round_width() { return kB; }
 
 int batched_resident_per_cu(DType dt)
 {

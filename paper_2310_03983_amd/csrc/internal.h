@@ -78,6 +78,19 @@ struct BatchArgs {
     uint32_t* counter;   // ticket counter, zeroed by launch_batched
 };
 
+// Device record of the batch buffers read by the lock-step kernels.
+struct BatchPtrs {
+    void* data;
+    const int64_t* offsets;
+    const int32_t* sizes;
+};
+hipError_t launch_batch_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, const int32_t* sizes,
+                             hipStream_t st);
+// phase 0: pivot closures; 1: panel tiles; 2: remainder tiles (items: int4 {graph, round, a, b}).
+hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const int4* items, int count,
+                              hipStream_t st);
+int batched_round_width();
+
 // Enqueues the counter reset and the persistent batched kernel.
 hipError_t launch_batched(DType dt, const BatchArgs& a, int grid, hipStream_t st);
 int batched_resident_per_cu(DType dt);

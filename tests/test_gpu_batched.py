@@ -39,23 +39,21 @@ def test_batched_edge_sizes(native, dev):
     rng = np.random.default_rng(900)
     sizes = [0, 1, 2, 3, 31, 127, 128, 129, 200, 255, 256, 257, 511, 512, 513, 1000, 1024, 5]
     mats = [rand_graph(rng, n, min(0.5, 3.0 / max(n, 1))) for n in sizes]
-    for flags in ({}, {"graph": False}, {"per_graph": True}):
+    for kw in ({}, {"batch_graph": False}, {"batch_persistent": True},
+               {"batch_persistent": True, "batch_graph": False}, {"batch_per_graph": True}):
         flat, off_d, sz_d, hs, off = pack(mats, dev)
-        kw = {}
-        if flags.get("graph") is False:
-            kw["batch_graph"] = False
-        if flags.get("per_graph"):
-            kw["batch_per_graph"] = True
+        flags = kw
         native.apsp_batched(flat, off_d, sz_d, hs, **kw)
         for W, got in zip(mats, unpack(flat, off, hs)):
             np.testing.assert_array_equal(got, oracle.fw_i32(W), err_msg=f"n={W.shape[0]} {flags}")
 
 
-def test_batched_f32(native, dev):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_f32(native, dev, persistent):
     rng = np.random.default_rng(901)
     mats = [rand_graph(rng, n, 4.0 / n, dtype="f32") for n in (40, 130, 300, 77)]
     flat, off_d, sz_d, hs, off = pack(mats, dev)
-    native.apsp_batched(flat, off_d, sz_d, hs)
+    native.apsp_batched(flat, off_d, sz_d, hs, batch_persistent=persistent)
     for W, got in zip(mats, unpack(flat, off, hs)):
         ref = oracle.fw_f64(W.astype(np.float64))
         assert np.array_equal(np.isinf(got), np.isinf(ref))
@@ -63,7 +61,8 @@ def test_batched_f32(native, dev):
         assert (np.abs(got[fin] - ref[fin]) <= 1e-5 * ref[fin]).all()
 
 
-def test_batched_graph_replays_and_buffer_swaps(native, dev):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_graph_replays_and_buffer_swaps(native, dev, persistent):
     # the captured launch is replayed several times, on two different buffers,
     # with unrelated eager work and synchronisations in between
     rng = np.random.default_rng(902)
@@ -73,7 +72,7 @@ def test_batched_graph_replays_and_buffer_swaps(native, dev):
     for rep in range(4):
         flat, off_d, sz_d, hs, off = bufs[rep % 2]
         flat.copy_(torch.from_numpy(gg.pack_batch(mats)[0]).to(dev))
-        native.apsp_batched(flat, off_d, sz_d, hs)
+        native.apsp_batched(flat, off_d, sz_d, hs, batch_persistent=persistent)
         junk = torch.arange(1000, device=dev).sum()   # eager work between replays
         torch.cuda.synchronize()
         assert int(junk) == 499500
@@ -81,11 +80,12 @@ def test_batched_graph_replays_and_buffer_swaps(native, dev):
             np.testing.assert_array_equal(got, ref, err_msg=f"replay {rep}")
 
 
-def test_batched_workload_512(native, dev):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_workload_512(native, dev, persistent):
     batch = gg.batch_ragged()
     mats = [gg.batch_graph_i32(b) for b in batch]
     flat, off_d, sz_d, hs, off = pack(mats, dev)
-    native.apsp_batched(flat, off_d, sz_d, hs)
+    native.apsp_batched(flat, off_d, sz_d, hs, batch_persistent=persistent)
     got = unpack(flat, off, hs)
     for b, W, g in zip(batch, mats, got):
         np.testing.assert_array_equal(g, oracle.fw_i32(W, threads=8), err_msg=f"graph {b.g} n={b.n}")

@@ -371,3 +371,21 @@ def test_predecessor_walks_have_the_shortest_length(oracle):
             for j in range(n):
                 w = oracle.walk_weight(W, bad, i, j)
                 assert w is None or w == D[i, j]
+
+
+# ---------------------------------------------------------------------------
+# property-based: Floyd-Warshall equals exhaustive enumeration
+# ---------------------------------------------------------------------------
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=150, deadline=None)
+@given(st.integers(1, 6).flatmap(lambda n: st.lists(
+    st.lists(st.one_of(st.just(INF), st.integers(0, 50), st.integers(400_000_000, INF - 1)), min_size=n, max_size=n),
+    min_size=n, max_size=n)))
+def test_fw_property_bruteforce(rows):
+    import oracle
+    W = np.array(rows, dtype=np.int32)
+    np.fill_diagonal(W, 0)
+    np.testing.assert_array_equal(oracle.fw_i32(W), np.array(oracle.brute_apsp(W.tolist()), dtype=np.int64))
