@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-graph batched measurement")
     ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--packed16", action="store_true",
+                    help="time the solve with APSP_FLAG_PACKED16 (int32 in and out, products in capped 16-bit "
+                         "arithmetic) instead of the int32 products")
     return ap.parse_args()
 
 
@@ -65,6 +68,38 @@ def time_steps(torch, fn, inputs, steps, warmup):
         fn(inputs[warmup + s])
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def bench_packed16(torch, apsp, Wd, n, cutover):
+    """The headline graph through R-Kleene with APSP_FLAG_PACKED16 (int32 data,
+    products in capped 16-bit arithmetic, exact int32 result): time per
+    solve (including the cap check and its host synchronisation), whether
+    the int32 redo ran, the 16-bit product kernel's rate, and a bit-for-bit
+    comparison with the int32 solver's output."""
+    def fn(d):
+        apsp.apsp_rkleene(d, cutover=cutover, packed16=True)
+    runs0, redone0 = apsp.apsp_packed16_counts()
+    ins = [Wd.clone() for _ in range(4)]
+    t = time_steps(torch, fn, ins, 3, 1)
+    runs1, redone1 = apsp.apsp_packed16_counts()
+    ins[0].copy_(Wd)
+    apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_128])
+    fn(ins[0])
+    torch.cuda.synchronize()
+    k = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_128)
+    apsp.apsp_profile_enable(False)
+    ref = Wd.clone()
+    apsp.apsp_rkleene(ref, cutover=cutover)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(ref, ins[0]))
+    del ins, ref
+    torch.cuda.empty_cache()
+    return {"ms_per_step": t * 1e3 / 3, "updates_per_s": n ** 3 / (t / 3),
+            "solves": runs1 - runs0, "int32_redone": redone1 - redone0,
+            "bit_identical_to_int32": same,
+            "minplus128_terms_per_s": k["terms"] / (k["ms"] / 1e3) if k["ms"] else None,
+            "note": "int32 in and out; products fold 4 terms in 3 instructions (capped 16-bit); "
+                    "exact, checked by counting capped entries after the solve"}
 
 
 def bench_batched(torch, np, apsp, gg, dev, steps):
@@ -131,18 +166,21 @@ def bench_batched(torch, np, apsp, gg, dev, steps):
     return out
 
 
-def counter_traffic():
-    """HBM bytes per launch of the 128x128 int32 kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source has changed
-    since the counters were taken."""
+def counter_traffic(packed16=False):
+    """HBM bytes per launch of the 128x128 product kernel from the committed
+    rocprofv3 counter summary, or None when the kernel sources have changed
+    since the counters were taken (sha256 over the listed files in order)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "minplus128_n16384_i32_traffic.json")
+    name = "minplus128p16" if packed16 else "minplus128"
+    path = os.path.join(ROOT, "profiles", f"{name}_n16384_i32_traffic.json")
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if h.hexdigest() != rec.get("sources_sha256"):
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -189,7 +227,10 @@ def main():
     viol = apsp.apsp_validate(Wd)
     if viol:
         raise SystemExit(f"input violates the contract in {viol} entries")
-    solve = {"rkleene": apsp.apsp_rkleene, "fw": apsp.apsp_fw, "solve": apsp.apsp_solve}[args.algo]
+    solve0 = {"rkleene": apsp.apsp_rkleene, "fw": apsp.apsp_fw, "solve": apsp.apsp_solve}[args.algo]
+
+    def solve(d, **kw):
+        return solve0(d, packed16=args.packed16, **kw)
     copies = [Wd.clone() for _ in range(args.steps + args.warmup)]
     # calibration for the HBM byte counters: one elementwise kernel that
     # reads n*n*4 bytes and writes n*n*4 bytes (outside the timed region)
@@ -238,25 +279,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "u16x2 capped (int32 in/out)" if args.packed16 else "int32",
         "data": "synthetic (seeded Bernoulli graph generator)",
-        "config": {"workload": f"apsp_{wl.name}_{args.algo}", "n": n, "p": wl.p, "cutover": args.cutover,
+        "config": {"workload": f"apsp_{wl.name}_{args.algo}" + ("_packed16" if args.packed16 else ""),
+                   "n": n, "p": wl.p, "cutover": args.cutover,
                    "weights": f"int32 uniform [{int(wl.lo)}, {int(wl.hi)}]", "inf": 2 ** 30,
                    "parallelism": "single GPU"},
         "valu_roofline_frac": 2.0 * value / VALU_PEAK_OPS,
         "roofline": {
             "bound": "alu",
-            "kernel": "k_minplus<int32, 128x128 tile>",
+            "kernel": "k_minplus<int32 data, capped 16-bit products, 128x128 tile>" if args.packed16
+                      else "k_minplus<int32, 128x128 tile>",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": counter_traffic(),
+            "traffic": counter_traffic(args.packed16),
             "launches": k128["launches"],
             "avg_launch_ms": avg_ms,
             "ops_per_launch": ops_per_launch,
-            "note": "ops = 2 per min-plus term (add + min); one 64-bit add forms two 32-bit sums and one "
-                    "v_min3 folds two terms, so frac can exceed 1 against the 32-bit lane-op peak",
+            "note": ("ops = 2 per min-plus term (add + min); one 64-bit add forms four 16-bit sums and two "
+                     "v_pk_min_u16 fold them, so frac can exceed 1 against the 32-bit lane-op peak")
+                    if args.packed16 else
+                    ("ops = 2 per min-plus term (add + min); one 64-bit add forms two 32-bit sums and one "
+                     "v_min3 folds two terms, so frac can exceed 1 against the 32-bit lane-op peak"),
         },
         "kernel_ms_per_solve": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in shares.items()},
     }
@@ -275,6 +321,7 @@ def main():
             extras[label] = {"ms_per_step": t * 1e3 / 3, "updates_per_s": n ** 3 / (t / 3)}
             del ins, src
             torch.cuda.empty_cache()
+        extras["rkleene_i32_packed16"] = bench_packed16(torch, apsp, Wd, n, args.cutover)
         result["extras"] = extras
 
     if not args.no_batched:

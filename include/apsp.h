@@ -77,6 +77,8 @@ typedef int32_t apsp_dtype_t;
 #define APSP_FLAG_BATCH_PER_GRAPH  4  /* apsp_batched: one launch per graph */
 #define APSP_FLAG_NO_LOOKAHEAD     8  /* blocked FW: strictly sequential rounds on the caller's stream */
 #define APSP_FLAG_BATCH_PERSISTENT 16 /* apsp_batched: one persistent kernel, one workgroup per graph */
+#define APSP_FLAG_PACKED16         32 /* int32 apsp_fw / apsp_rkleene / apsp_square / apsp_solve:
+                                         min-plus products in capped 16-bit arithmetic (see below) */
 
 typedef struct apsp_opts {
     int32_t algo;      /* APSP_ALGO_*; only apsp_solve and apsp_batched read it */
@@ -161,6 +163,24 @@ apsp_status_t apsp_rkleene(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  */
 apsp_status_t apsp_square(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                           void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/*
+ * APSP_FLAG_PACKED16 (int32 only; other dtypes: APSP_E_UNSUPPORTED, and
+ * minplus_gemm / apsp_closure / apsp_batched reject it).  The min-plus
+ * products of apsp_fw / apsp_rkleene / apsp_square stage every value capped
+ * at 2^15 - 1 and fold four reduction steps with one 64-bit add and two
+ * packed 16-bit minima, a third fewer instructions per term than int32; the
+ * matrix in memory stays int32.  Capping commutes with min and +, so an
+ * entry below the cap is exact.  After the solve one pass counts entries
+ * >= 2^15 - 1 and reads the count back (the call then returns with `stream`
+ * synchronised); if there are any, the int32 solver runs once more on the
+ * result, which yields the exact int32 closure.  The output is therefore
+ * identical to the int32 solver's in every case; the mode pays off when all
+ * distances are below 32767 and every vertex reaches every other.
+ * apsp_packed16_counts reports how many solves used the mode and how many
+ * of them were redone.
+ */
+apsp_status_t apsp_packed16_counts(apsp_ctx_t *ctx, int64_t *runs, int64_t *redone);
 
 /* Dispatches to apsp_fw / apsp_rkleene / apsp_square per opts->algo; with
  * APSP_ALGO_AUTO (or opts == NULL) the size rule decides: blocked FW up to

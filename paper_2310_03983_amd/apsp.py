@@ -24,6 +24,8 @@ ALGO = {"auto": 0, "fw": 1, "rkleene": 2, "square": 3}
 CLOSURE = {"auto": 0, "kloop": 1, "square": 2}
 TILE = {"auto": 0, 128: 1, 64: 2}
 FLAG_NO_SPLITK, FLAG_BATCH_NO_GRAPH, FLAG_BATCH_PER_GRAPH, FLAG_NO_LOOKAHEAD, FLAG_BATCH_PERSISTENT = 1, 2, 4, 8, 16
+FLAG_PACKED16 = 32
+CAP16 = 0x7FFF
 
 # every symbol include/apsp.h declares
 EXPORTS = [
@@ -33,6 +35,7 @@ EXPORTS = [
     "apsp_candidate_count", "apsp_candidate", "apsp_costmodel_init", "apsp_costmodel_set_norm",
     "apsp_costmodel_set_params", "apsp_costmodel_get_params", "apsp_costmodel_train", "apsp_costmodel_grad",
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
+    "apsp_packed16_counts",
 ]
 
 KERNEL_MINPLUS_128, KERNEL_MINPLUS_64, KERNEL_CLOSURE, KERNEL_OTHER = 0, 1, 2, 3
@@ -62,7 +65,8 @@ class KernelStats(ctypes.Structure):
 
 
 def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True,
-              batch_graph=True, batch_per_graph=False, lookahead=True, batch_persistent=False) -> Opts:
+              batch_graph=True, batch_per_graph=False, lookahead=True, batch_persistent=False,
+              packed16=False) -> Opts:
     o = Opts()
     o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
     o.block = int(block)
@@ -71,7 +75,7 @@ def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, spli
     o.cutover = int(cutover)
     o.flags = (0 if splitk else FLAG_NO_SPLITK) | (0 if batch_graph else FLAG_BATCH_NO_GRAPH) | \
         (FLAG_BATCH_PER_GRAPH if batch_per_graph else 0) | (0 if lookahead else FLAG_NO_LOOKAHEAD) | \
-        (FLAG_BATCH_PERSISTENT if batch_persistent else 0)
+        (FLAG_BATCH_PERSISTENT if batch_persistent else 0) | (FLAG_PACKED16 if packed16 else 0)
     return o
 
 
@@ -318,6 +322,13 @@ def apsp_profile_read(kind: int, device: int | None = None) -> dict:
     st = KernelStats()
     _check(lib().apsp_profile_read(context(device), kind, ctypes.byref(st)))
     return {"launches": st.launches, "ms": st.milliseconds, "terms": st.terms, "bytes": st.bytes}
+
+
+def apsp_packed16_counts(device: int | None = None) -> tuple[int, int]:
+    """(solves run with packed16=True, how many of them were redone in int32)."""
+    runs, redone = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().apsp_packed16_counts(context(device), ctypes.byref(runs), ctypes.byref(redone)))
+    return runs.value, redone.value
 
 
 # ---------------------------------------------------------------------------

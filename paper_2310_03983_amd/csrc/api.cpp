@@ -66,6 +66,8 @@ struct apsp_ctx {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
+    int64_t p16_runs = 0;           // solves run with APSP_FLAG_PACKED16
+    int64_t p16_redone = 0;         // ... of which were redone in int32
     uint32_t magic = 0x41505350;    // "APSP"
 };
 
@@ -199,6 +201,7 @@ struct Plan {
     int cutover;    // R-Kleene -> FW below this size
     bool splitk;
     bool lookahead; // FW: overlap the next pivot and panels with the remainder
+    bool p16;       // int32: min-plus products in capped 16-bit arithmetic
 };
 
 Plan resolve(const apsp_opts_t* o)
@@ -210,7 +213,14 @@ Plan resolve(const apsp_opts_t* o)
     p.cutover = o->cutover;
     p.splitk = !(o->flags & APSP_FLAG_NO_SPLITK);
     p.lookahead = !(o->flags & APSP_FLAG_NO_LOOKAHEAD);
+    p.p16 = (o->flags & APSP_FLAG_PACKED16) != 0;
     return p;
+}
+
+// element semantics of the min-plus products of a plan
+apsp::DType gemm_dtype(apsp_dtype_t dt, const Plan& pl)
+{
+    return pl.p16 ? apsp::I32P16 : (apsp::DType)dt;
 }
 
 apsp::GemmProblem make_problem(apsp_dtype_t dt, void* base, int64_t ld,
@@ -246,12 +256,13 @@ apsp_status_t run_group(apsp_ctx_t* ctx, apsp_dtype_t dt, apsp::GemmGroup& g, co
                         int tile, hipStream_t st)
 {
     if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
-    apsp::finalize_group(g, tile, pl.splitk ? 2 * ctx->num_cus : 0);
+    const apsp::DType gdt = gemm_dtype(dt, pl);
+    apsp::finalize_group(g, tile, pl.splitk ? 2 * ctx->num_cus : 0, gdt);
     double terms, bytes;
     group_work(g, tile, terms, bytes);
     const int kind = tile == apsp::TILE_64 ? APSP_KERNEL_MINPLUS_64 : APSP_KERNEL_MINPLUS_128;
     return timed(ctx, kind, terms, bytes, st, [&]() -> apsp_status_t {
-        HIP_TRY(apsp::launch_minplus((apsp::DType)dt, tile, g, st), "min-plus launch");
+        HIP_TRY(apsp::launch_minplus(gdt, tile, g, st), "min-plus launch");
         return APSP_OK;
     });
 }
@@ -459,7 +470,7 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
         const double terms = (double)n * n * n;
         rc = timed(ctx, tile == apsp::TILE_64 ? APSP_KERNEL_MINPLUS_64 : APSP_KERNEL_MINPLUS_128, terms,
                    16.0 * n * n, st, [&]() -> apsp_status_t {
-                       HIP_TRY(apsp::launch_square_pass((apsp::DType)dt, tile, D, n, ld, flag, st),
+                       HIP_TRY(apsp::launch_square_pass(gemm_dtype(dt, pl), tile, D, n, ld, flag, st),
                                "squaring pass");
                        return APSP_OK;
                    });
@@ -471,6 +482,43 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
         if (!h) break;
         if (passes > 64) return fail(APSP_E_INPUT, "squaring did not converge (negative costs?)");
     }
+    return APSP_OK;
+}
+
+// APSP_FLAG_PACKED16 epilogue.  The products ran in arithmetic capped at
+// 2^15 - 1; capping commutes with min and +, so every stored value below the
+// cap is an exact distance, and every stored value is the length of a real
+// walk (or INF) and no larger than the input entry.  If no entry reached the
+// cap the result is therefore the int32 result.  Otherwise the int32 solver
+// runs again on the stored matrix: it lies between the true distances and
+// the input, so its closure is the true one.
+template <class Redo>
+apsp_status_t finish_packed16(apsp_ctx_t* ctx, int64_t n, const void* D, int64_t ld, hipStream_t st,
+                              Redo&& redo)
+{
+    ++ctx->p16_runs;
+    auto* cnt = reinterpret_cast<unsigned long long*>(static_cast<uint32_t*>(ctx->d_scratch) + 16);
+    HIP_TRY(apsp::launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 2, st), "counter reset");
+    HIP_TRY(apsp::launch_count_ge(static_cast<const uint32_t*>(D), n, ld, apsp::kCap16, cnt, st), "cap count");
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st), "cap count copy");
+    HIP_TRY(hipStreamSynchronize(st), "cap count sync");
+    if (!h) return APSP_OK;
+    ++ctx->p16_redone;
+    return redo();
+}
+
+apsp_status_t check_packed16(apsp_dtype_t dt, const apsp_opts_t* o)
+{
+    if ((o->flags & APSP_FLAG_PACKED16) && dt != APSP_I32)
+        return fail(APSP_E_UNSUPPORTED, "APSP_FLAG_PACKED16 needs int32 data");
+    return APSP_OK;
+}
+
+apsp_status_t reject_packed16(const apsp_opts_t* o, const char* who)
+{
+    if (o->flags & APSP_FLAG_PACKED16)
+        return fail(APSP_E_UNSUPPORTED, "APSP_FLAG_PACKED16 is not available for %s", who);
     return APSP_OK;
 }
 
@@ -596,7 +644,7 @@ apsp_status_t minplus_gemm(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t m, int64_t 
     apsp_status_t rc;
     if ((rc = check_dtype(dt))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o))) return rc;
+    if ((rc = check_opts(o)) || (rc = reject_packed16(o, "minplus_gemm"))) return rc;
     if (m < 0 || n < 0 || k < 0) return fail(APSP_E_ARG, "negative size m=%lld n=%lld k=%lld",
                                              (long long)m, (long long)n, (long long)k);
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2) return fail(APSP_E_ARG, "size too large");
@@ -623,7 +671,7 @@ apsp_status_t apsp_closure(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D,
     apsp_status_t rc;
     if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_opts(o)) || (rc = reject_packed16(o, "apsp_closure")) || (rc = check_ctx(ctx))) return rc;
     if (n > 128) return fail(APSP_E_UNSUPPORTED, "closure block n = %lld > 128", (long long)n);
     if (n <= 1) return APSP_OK;
     const Plan pl = resolve(o);
@@ -636,10 +684,15 @@ apsp_status_t apsp_fw(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int6
     apsp_status_t rc;
     if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_opts(o)) || (rc = check_packed16(dt, o)) || (rc = check_ctx(ctx))) return rc;
     if (n <= 1) return APSP_OK;
-    const Plan pl = resolve(o);
-    return fw_window(ctx, dt, D, ldd, 0, n, pl, static_cast<hipStream_t>(stream));
+    Plan pl = resolve(o);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = fw_window(ctx, dt, D, ldd, 0, n, pl, st)) || !pl.p16) return rc;
+    return finish_packed16(ctx, n, D, ldd, st, [&] {
+        pl.p16 = false;
+        return fw_window(ctx, dt, D, ldd, 0, n, pl, st);
+    });
 }
 
 apsp_status_t apsp_rkleene(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
@@ -648,10 +701,15 @@ apsp_status_t apsp_rkleene(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D,
     apsp_status_t rc;
     if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_opts(o)) || (rc = check_packed16(dt, o)) || (rc = check_ctx(ctx))) return rc;
     if (n <= 1) return APSP_OK;
-    const Plan pl = resolve(o);
-    return rk_window(ctx, dt, D, ldd, 0, n, pl, static_cast<hipStream_t>(stream));
+    Plan pl = resolve(o);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = rk_window(ctx, dt, D, ldd, 0, n, pl, st)) || !pl.p16) return rc;
+    return finish_packed16(ctx, n, D, ldd, st, [&] {
+        pl.p16 = false;
+        return rk_window(ctx, dt, D, ldd, 0, n, pl, st);
+    });
 }
 
 apsp_status_t apsp_square(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
@@ -660,9 +718,25 @@ apsp_status_t apsp_square(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, 
     apsp_status_t rc;
     if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
-    const Plan pl = resolve(o);
-    return square_common(ctx, dt, n, D, ldd, pl, static_cast<hipStream_t>(stream));
+    if ((rc = check_opts(o)) || (rc = check_packed16(dt, o)) || (rc = check_ctx(ctx))) return rc;
+    if (n <= 1) return APSP_OK;
+    Plan pl = resolve(o);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = square_common(ctx, dt, n, D, ldd, pl, st)) || !pl.p16) return rc;
+    return finish_packed16(ctx, n, D, ldd, st, [&] {
+        pl.p16 = false;
+        return square_common(ctx, dt, n, D, ldd, pl, st);
+    });
+}
+
+apsp_status_t apsp_packed16_counts(apsp_ctx_t* ctx, int64_t* runs, int64_t* redone)
+{
+    apsp_status_t rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!runs || !redone) return fail(APSP_E_ARG, "NULL output pointer");
+    *runs = ctx->p16_runs;
+    *redone = ctx->p16_redone;
+    return APSP_OK;
 }
 
 apsp_status_t apsp_solve(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ldd,
@@ -671,7 +745,7 @@ apsp_status_t apsp_solve(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, i
     apsp_status_t rc;
     if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_opts(o)) || (rc = check_packed16(dt, o)) || (rc = check_ctx(ctx))) return rc;
     switch (o->algo) {
     case APSP_ALGO_FW: return apsp_fw(ctx, dt, n, D, ldd, o, stream);
     case APSP_ALGO_SQUARE: return apsp_square(ctx, dt, n, D, ldd, o, stream);
@@ -739,7 +813,7 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
     apsp_status_t rc;
     if ((rc = check_dtype(dt))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o))) return rc;
+    if ((rc = check_opts(o)) || (rc = reject_packed16(o, "apsp_batched"))) return rc;
     if (count < 0) return fail(APSP_E_ARG, "count = %d is negative", count);
     if (count > 0 && (!data || !d_offsets || !d_sizes || !h_sizes))
         return fail(APSP_E_ARG, "NULL batch pointer");

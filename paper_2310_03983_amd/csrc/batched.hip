@@ -126,7 +126,8 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
 // device record so that a captured launch sequence serves any buffers.
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ __launch_bounds__(256) void k_bclose(const BatchPtrs* __restrict__ bp, const int4* __restrict__ items)
+__global__ __launch_bounds__(dev::kCloseWideThreads) void k_bclose(const BatchPtrs* __restrict__ bp,
+                                                                   const int4* __restrict__ items)
 {
     using T = typename S::T;
     __shared__ __attribute__((aligned(16))) T lds[dev::kCloseLdsWords];
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void k_bclose(const BatchPtrs* __restrict__ bp
     const int n = bp->sizes[it.x];
     T* D = static_cast<T*>(bp->data) + bp->offsets[it.x];
     const int k0 = it.y * kB;
-    dev::close_block<S>(D + (int64_t)k0 * n + k0, n, min(kB, n - k0), lds);
+    dev::close_block_wide<S>(D + (int64_t)k0 * n + k0, n, min(kB, n - k0), lds);
 }
 
 template <class S>
@@ -224,9 +225,9 @@ hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const in
     if (count <= 0) return hipSuccess;
     if (phase == 0) {
         if (dt == I32)
-            hipLaunchKernelGGL(k_bclose<dev::SemI32>, dim3(count), dim3(256), 0, st, bp, items);
+            hipLaunchKernelGGL(k_bclose<dev::SemI32>, dim3(count), dim3(dev::kCloseWideThreads), 0, st, bp, items);
         else
-            hipLaunchKernelGGL(k_bclose<dev::SemF32>, dim3(count), dim3(256), 0, st, bp, items);
+            hipLaunchKernelGGL(k_bclose<dev::SemF32>, dim3(count), dim3(dev::kCloseWideThreads), 0, st, bp, items);
     } else {
         if (dt == I32)
             hipLaunchKernelGGL(k_btile<dev::SemI32>, dim3(count), dim3(256), 0, st, bp, items, phase);

@@ -23,10 +23,11 @@ using CI32 = dev::SemI32;
 using CF32 = dev::SemF32;
 
 template <class S>
-__global__ __launch_bounds__(256) void k_closure_kloop(typename S::T* __restrict__ D, int64_t ld, int s)
+__global__ __launch_bounds__(dev::kCloseWideThreads) void k_closure_kloop(typename S::T* __restrict__ D, int64_t ld,
+                                                                          int s)
 {
     __shared__ __attribute__((aligned(16))) typename S::T lds[dev::kCloseLdsWords];
-    dev::close_block<S>(D, ld, s, lds);
+    dev::close_block_wide<S>(D, ld, s, lds);
 }
 
 template <class S>
@@ -122,6 +123,19 @@ __global__ void k_validate<CF32>(const float* __restrict__ D, int64_t n, int64_t
     if (bad) atomicAdd(count, bad);
 }
 
+__global__ void k_count_ge(const uint32_t* __restrict__ D, int64_t n, int64_t ld, uint32_t thr,
+                           unsigned long long* __restrict__ count)
+{
+    unsigned long long hits = 0;
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / n, c = e - r * n;
+        if (D[r * ld + c] >= thr) ++hits;
+    }
+    if (hits) atomicAdd(count, hits);
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
@@ -141,9 +155,9 @@ hipError_t launch_closure(DType dt, int kind, void* D, int64_t ld, int32_t s, hi
             hipLaunchKernelGGL(k_closure_square<CF32>, dim3(1), dim3(256), 0, st, (float*)D, ld, s);
     } else {
         if (dt == I32)
-            hipLaunchKernelGGL(k_closure_kloop<CI32>, dim3(1), dim3(256), 0, st, (uint32_t*)D, ld, s);
+            hipLaunchKernelGGL(k_closure_kloop<CI32>, dim3(1), dim3(dev::kCloseWideThreads), 0, st, (uint32_t*)D, ld, s);
         else
-            hipLaunchKernelGGL(k_closure_kloop<CF32>, dim3(1), dim3(256), 0, st, (float*)D, ld, s);
+            hipLaunchKernelGGL(k_closure_kloop<CF32>, dim3(1), dim3(dev::kCloseWideThreads), 0, st, (float*)D, ld, s);
     }
     return hipGetLastError();
 }
@@ -161,6 +175,16 @@ hipError_t launch_validate(DType dt, const void* D, int64_t n, int64_t ld,
     else
         hipLaunchKernelGGL(k_validate<CF32>, dim3((unsigned)blocks), dim3(256), 0, st,
                            (const float*)D, n, ld, d_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_ge(const uint32_t* D, int64_t n, int64_t ld, uint32_t thr,
+                           unsigned long long* d_count, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t total = n * n;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_count_ge, dim3((unsigned)blocks), dim3(256), 0, st, D, n, ld, thr, d_count);
     return hipGetLastError();
 }
 

@@ -10,10 +10,18 @@ namespace dev {
 
 constexpr int kMaxS = 128;   // largest block closed inside one workgroup
 
+// A semiring policy gives: the element type T in memory, the packed LDS
+// operand P holding KPACK consecutive reduction steps, the accumulator type
+// A, and fold(acc, a, b) = min(acc, a_t + b_t over the KPACK steps).
+// acc_from maps a C value to an accumulator, acc_value maps it back.
 struct SemI32 {
     using T = uint32_t;
     using P = uint64_t;
+    using A = uint32_t;
+    static constexpr int KPACK = 2;
     static __device__ __forceinline__ T inf() { return kInfI32; }
+    static __device__ __forceinline__ A acc_from(T c) { return c; }
+    static __device__ __forceinline__ T acc_value(A a) { return a; }
     static __device__ __forceinline__ P pack(T lo, T hi) { return ((P)hi << 32) | (P)lo; }
     static __device__ __forceinline__ P pair(T lo, T hi) { return pack(lo, hi); }
     // one term: saturation is implicit (operands <= 2^30, accumulator <= INF)
@@ -33,7 +41,11 @@ struct SemI32 {
 struct SemF32 {
     using T = float;
     using P = float2;
+    using A = float;
+    static constexpr int KPACK = 2;
     static __device__ __forceinline__ T inf() { return __builtin_inff(); }
+    static __device__ __forceinline__ A acc_from(T c) { return c; }
+    static __device__ __forceinline__ T acc_value(A a) { return a; }
     static __device__ __forceinline__ P pack(T lo, T hi) { return make_float2(lo, hi); }
     static __device__ __forceinline__ P pair(T lo, T hi) { return pack(lo, hi); }
     static __device__ __forceinline__ T relax(T x, T a, T b) { return fminf(x, a + b); }
@@ -49,6 +61,61 @@ struct SemF32 {
     static __device__ __forceinline__ void atomic_min(T* p, T v) {
         atomicMin(reinterpret_cast<int*>(p), __float_as_int(v));
     }
+};
+
+// int32 distances folded in capped 16-bit arithmetic.  Every value v is
+// staged as min(v, kCap16), kCap16 = 2^15 - 1 standing for "no path"; four
+// consecutive reduction steps share one 64-bit LDS word.  One 64-bit add then
+// forms four 16-bit sums (each <= 2 kCap16 < 2^16, so no carry crosses a
+// lane) and two v_pk_min_u16 fold them into an accumulator of two 16-bit
+// partial minima (even / odd steps): 3 instructions per 4 terms.
+// Capping commutes with min and with saturating addition,
+//   min(a + b, cap) = min(min(a, cap) + min(b, cap), cap)   (a, b >= 0),
+// so the folded value is exactly min(true value, kCap16).  acc_value widens
+// kCap16 back to INF; the product's epilogue keeps the old C entry whenever
+// that is smaller (a capped result says only "not below kCap16").
+struct SemU16 {
+    using T = uint32_t;
+    using P = uint64_t;
+    using A = uint32_t;
+    static constexpr int KPACK = 4;
+    static constexpr uint32_t kCap16 = apsp::kCap16;
+    static __device__ __forceinline__ T inf() { return kInfI32; }
+    static __device__ __forceinline__ uint32_t narrow(T v) { return min(v, kCap16); }
+    static __device__ __forceinline__ P quad(T x0, T x1, T x2, T x3) {
+        const uint32_t lo = narrow(x0) | (narrow(x1) << 16);
+        const uint32_t hi = narrow(x2) | (narrow(x3) << 16);
+        return ((P)hi << 32) | (P)lo;
+    }
+    static __device__ __forceinline__ A acc_from(T c) { return narrow(c) * 0x10001u; }
+    static __device__ __forceinline__ T acc_value(A a) {
+        const uint32_t r = min(a & 0xffffu, a >> 16);
+        return r < kCap16 ? r : kInfI32;
+    }
+    using U2 = unsigned short __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ A fold(A acc, P a, P b) {
+        const P s = a + b;
+        const U2 lo = __builtin_bit_cast(U2, (uint32_t)s);
+        const U2 hi = __builtin_bit_cast(U2, (uint32_t)(s >> 32));
+        const U2 m = __builtin_elementwise_min(lo, hi);
+        return __builtin_bit_cast(A, __builtin_elementwise_min(__builtin_bit_cast(U2, acc), m));
+    }
+    // Two outputs sharing the A operand, interleaved so that no packed
+    // result is read by the very next instruction: the compiler pads such
+    // back-to-back packed dependences with a wait state, and left to itself
+    // (under register pressure) it chains every fold that way.  The
+    // accumulators written here are next read a whole register tile later.
+    static __device__ __forceinline__ void fold2(A& acc0, A& acc1, P a, P b0, P b1) {
+        const P s0 = a + b0, s1 = a + b1;
+        uint32_t m0, m1;
+        asm("v_pk_min_u16 %0, %4, %5\n\t"
+            "v_pk_min_u16 %1, %6, %7\n\t"
+            "v_pk_min_u16 %2, %2, %0\n\t"
+            "v_pk_min_u16 %3, %3, %1"
+            : "=&v"(m0), "=&v"(m1), "+v"(acc0), "+v"(acc1)
+            : "v"((uint32_t)s0), "v"((uint32_t)(s0 >> 32)), "v"((uint32_t)s1), "v"((uint32_t)(s1 >> 32)));
+    }
+    static __device__ __forceinline__ void atomic_min(T* p, T v) { atomicMin(p, v); }
 };
 
 template <class P>
@@ -83,7 +150,7 @@ struct Cfg {
     static constexpr int TX = NT / TN;
     static constexpr int TY = MT / TM;
     static constexpr int NTHR = TX * TY;
-    static constexpr int KP = KT / 2;
+    static constexpr int KP = KT / S::KPACK;   // packed reduction steps per slice
     static constexpr int GM = TM / 2;       // row groups of 2 per lane
     static constexpr int GN = TN / 2;
     static constexpr int SM = MT / GM;      // stride between a lane's row groups
@@ -91,9 +158,12 @@ struct Cfg {
     static constexpr int PADP = 2;          // pairs of padding per LDS row
     static constexpr int LDA = MT + PADP;
     static constexpr int LDB = NT + PADP;
-    // staging work per lane
+    // staging work per lane.  B is staged in (packed row, BV columns)
+    // pieces: 4 columns, or 2 when four-step packing leaves too few packed
+    // rows per slice to give every lane a 4-column piece
     static constexpr int A_VECS = MT * KT / 4;          // float4-sized loads of A
-    static constexpr int B_COMBOS = KP * (NT / 4);      // (pair row, 4 columns) of B
+    static constexpr int BV = (KP * (NT / 4) < NTHR) ? 2 : 4;
+    static constexpr int B_COMBOS = KP * (NT / BV);     // (packed row, BV columns) of B
     static_assert(A_VECS % NTHR == 0, "A staging must divide evenly");
     static_assert(B_COMBOS % NTHR == 0, "B staging must divide evenly");
     static constexpr int A_PER = A_VECS / NTHR;
@@ -108,7 +178,8 @@ struct Cfg {
 // C already point at the (0, 0) element of their windows; m0/n0 are the tile
 // origin.  With atomic_out the tile's partial minimum is merged into C with
 // atomic min (split reduction); otherwise C is read once and written once.
-// As/Bs: LDS staging of 2 x KT/2 x (MT+2) and 2 x KT/2 x (NT+2) pairs.
+// As/Bs: LDS staging of 2 x KT/KPACK x (MT+2) and 2 x KT/KPACK x (NT+2)
+// packed words.
 // ---------------------------------------------------------------------------
 template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC>
 __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int64_t lda,
@@ -116,12 +187,14 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
                                         typename S::T* C, int64_t ldc, int M, int N,
                                         int m0, int n0, int kbeg, int kend, bool atomic_out,
                                         uint32_t* __restrict__ changed,
-                                        typename S::P (*As)[KT / 2][MT + 2],
-                                        typename S::P (*Bs)[KT / 2][NT + 2])
+                                        typename S::P (*As)[KT / S::KPACK][MT + 2],
+                                        typename S::P (*Bs)[KT / S::KPACK][NT + 2])
 {
     using C_ = Cfg<S, MT, NT, KT, TM, TN>;
     using T = typename S::T;
     using P = typename S::P;
+    using Acc = typename S::A;
+    constexpr int KPACK = S::KPACK;
     constexpr int KP = C_::KP;
     const int tid = threadIdx.x;
     const int tx = tid % C_::TX;
@@ -131,7 +204,7 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
     auto col_of = [&](int j) { return (j >> 1) * C_::SN + tx * 2 + (j & 1); };
 
     // ---- accumulators start at C (or INF for a partial-K split)
-    T acc[TM][TN];
+    Acc acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int r = m0 + row_of(i);
@@ -139,22 +212,23 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
         for (int j = 0; j < TN; j += 2) {
             const int c = n0 + col_of(j);
             if (atomic_out) {
-                acc[i][j] = S::inf();
-                acc[i][j + 1] = S::inf();
+                acc[i][j] = S::acc_from(S::inf());
+                acc[i][j + 1] = S::acc_from(S::inf());
             } else if (VEC && r < M && c + 1 < N) {
                 const auto v = ld_vec<Pair2<T>>(C + (int64_t)r * ldc + c);
-                acc[i][j] = v.x;
-                acc[i][j + 1] = v.y;
+                acc[i][j] = S::acc_from(v.x);
+                acc[i][j + 1] = S::acc_from(v.y);
             } else {
-                acc[i][j] = (r < M && c < N) ? C[(int64_t)r * ldc + c] : S::inf();
-                acc[i][j + 1] = (r < M && c + 1 < N) ? C[(int64_t)r * ldc + c + 1] : S::inf();
+                acc[i][j] = S::acc_from((r < M && c < N) ? C[(int64_t)r * ldc + c] : S::inf());
+                acc[i][j + 1] = S::acc_from((r < M && c + 1 < N) ? C[(int64_t)r * ldc + c + 1] : S::inf());
             }
         }
     }
 
     // ---- staging registers
     T ra[C_::A_PER][4];
-    T rb[C_::B_PER][2][4];
+    constexpr int BV = C_::BV;
+    T rb[C_::B_PER][KPACK][BV];
 
     auto load_slice = [&](int k0) {
 #pragma unroll
@@ -179,23 +253,32 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
 #pragma unroll
         for (int q = 0; q < C_::B_PER; ++q) {
             const int L = tid + q * C_::NTHR;
-            const int p = L / (NT / 4);
-            const int c4 = L % (NT / 4);
-            const int gc = n0 + c4 * 4;
+            const int p = L / (NT / BV);
+            const int cv = L % (NT / BV);
+            const int gc = n0 + cv * BV;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int gk = k0 + 2 * p + h;
-                if (VEC && gk < kend && gc + 3 < N) {
-                    const float4 v = ld_vec<float4>(B + (int64_t)gk * ldb + gc);
-                    rb[q][h][0] = __builtin_bit_cast(T, v.x);
-                    rb[q][h][1] = __builtin_bit_cast(T, v.y);
-                    rb[q][h][2] = __builtin_bit_cast(T, v.z);
-                    rb[q][h][3] = __builtin_bit_cast(T, v.w);
+            for (int h = 0; h < KPACK; ++h) {
+                const int gk = k0 + KPACK * p + h;
+                if constexpr (BV == 4) {
+                    if (VEC && gk < kend && gc + 3 < N) {
+                        const float4 v = ld_vec<float4>(B + (int64_t)gk * ldb + gc);
+                        rb[q][h][0] = __builtin_bit_cast(T, v.x);
+                        rb[q][h][1] = __builtin_bit_cast(T, v.y);
+                        rb[q][h][2] = __builtin_bit_cast(T, v.z);
+                        rb[q][h][3] = __builtin_bit_cast(T, v.w);
+                        continue;
+                    }
                 } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        rb[q][h][e] = (gk < kend && gc + e < N) ? B[(int64_t)gk * ldb + gc + e] : S::inf();
+                    if (VEC && gk < kend && gc + 1 < N) {
+                        const Pair2<T> v = ld_vec<Pair2<T>>(B + (int64_t)gk * ldb + gc);
+                        rb[q][h][0] = v.x;
+                        rb[q][h][1] = v.y;
+                        continue;
+                    }
                 }
+#pragma unroll
+                for (int e = 0; e < BV; ++e)
+                    rb[q][h][e] = (gk < kend && gc + e < N) ? B[(int64_t)gk * ldb + gc + e] : S::inf();
             }
         }
     };
@@ -206,21 +289,41 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
             const int L = tid + q * C_::NTHR;
             const int row = L / (KT / 4);
             const int c4 = L % (KT / 4);
-            As[buf][c4 * 2][row] = S::pack(ra[q][0], ra[q][1]);
-            As[buf][c4 * 2 + 1][row] = S::pack(ra[q][2], ra[q][3]);
+            if constexpr (KPACK == 2) {
+                As[buf][c4 * 2][row] = S::pack(ra[q][0], ra[q][1]);
+                As[buf][c4 * 2 + 1][row] = S::pack(ra[q][2], ra[q][3]);
+            } else {
+                As[buf][c4][row] = S::quad(ra[q][0], ra[q][1], ra[q][2], ra[q][3]);
+            }
         }
 #pragma unroll
         for (int q = 0; q < C_::B_PER; ++q) {
             const int L = tid + q * C_::NTHR;
-            const int p = L / (NT / 4);
-            const int c4 = L % (NT / 4);
-            Pair2<P> lo, hi;
-            lo.x = S::pack(rb[q][0][0], rb[q][1][0]);
-            lo.y = S::pack(rb[q][0][1], rb[q][1][1]);
-            hi.x = S::pack(rb[q][0][2], rb[q][1][2]);
-            hi.y = S::pack(rb[q][0][3], rb[q][1][3]);
-            *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4]) = lo;
-            *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4 + 2]) = hi;
+            if constexpr (BV == 2) {
+                const int p = L / (NT / 2);
+                const int c2 = L % (NT / 2);
+                Pair2<P> v;
+                v.x = S::quad(rb[q][0][0], rb[q][1][0], rb[q][2][0], rb[q][3][0]);
+                v.y = S::quad(rb[q][0][1], rb[q][1][1], rb[q][2][1], rb[q][3][1]);
+                *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c2 * 2]) = v;
+            } else {
+                const int p = L / (NT / 4);
+                const int c4 = L % (NT / 4);
+                Pair2<P> lo, hi;
+                if constexpr (KPACK == 2) {
+                    lo.x = S::pack(rb[q][0][0], rb[q][1][0]);
+                    lo.y = S::pack(rb[q][0][1], rb[q][1][1]);
+                    hi.x = S::pack(rb[q][0][2], rb[q][1][2]);
+                    hi.y = S::pack(rb[q][0][3], rb[q][1][3]);
+                } else {
+                    lo.x = S::quad(rb[q][0][0], rb[q][1][0], rb[q][2][0], rb[q][3][0]);
+                    lo.y = S::quad(rb[q][0][1], rb[q][1][1], rb[q][2][1], rb[q][3][1]);
+                    hi.x = S::quad(rb[q][0][2], rb[q][1][2], rb[q][2][2], rb[q][3][2]);
+                    hi.y = S::quad(rb[q][0][3], rb[q][1][3], rb[q][2][3], rb[q][3][3]);
+                }
+                *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4]) = lo;
+                *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c4 * 4 + 2]) = hi;
+            }
         }
     };
 
@@ -249,11 +352,18 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
                     b[2 * g] = v.x;
                     b[2 * g + 1] = v.y;
                 }
+                if constexpr (KPACK == 4) {
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
+                    for (int i = 0; i < TM; ++i)
 #pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
+                        for (int j = 0; j < TN; j += 2) S::fold2(acc[i][j], acc[i][j + 1], a[i], b[j], b[j + 1]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
+                }
             }
             if (s + 1 < nslices) store_slice(cur ^ 1);
             __syncthreads();
@@ -262,6 +372,48 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
 
     // ---- epilogue
     bool dec = false;
+    if constexpr (KPACK == 4) {
+        // capped accumulators: widen, then keep the old entry where it is
+        // smaller (a capped value only says "not below the cap")
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int r = m0 + row_of(i);
+#pragma unroll
+            for (int j = 0; j < TN; j += 2) {
+                const int c = n0 + col_of(j);
+                const T v0 = S::acc_value(acc[i][j]), v1 = S::acc_value(acc[i][j + 1]);
+                if (atomic_out) {
+                    if (r < M && c < N && v0 < S::inf()) S::atomic_min(C + (int64_t)r * ldc + c, v0);
+                    if (r < M && c + 1 < N && v1 < S::inf()) S::atomic_min(C + (int64_t)r * ldc + c + 1, v1);
+                    continue;
+                }
+                if (VEC && r < M && c + 1 < N) {
+                    Pair2<T> o = ld_vec<Pair2<T>>(C + (int64_t)r * ldc + c);
+                    if (v0 < o.x || v1 < o.y) dec = true;
+                    o.x = min(o.x, v0);
+                    o.y = min(o.y, v1);
+                    st_vec(C + (int64_t)r * ldc + c, o);
+                } else {
+                    if (r < M && c < N) {
+                        const T o = C[(int64_t)r * ldc + c];
+                        if (v0 < o) {
+                            dec = true;
+                            C[(int64_t)r * ldc + c] = v0;
+                        }
+                    }
+                    if (r < M && c + 1 < N) {
+                        const T o = C[(int64_t)r * ldc + c + 1];
+                        if (v1 < o) {
+                            dec = true;
+                            C[(int64_t)r * ldc + c + 1] = v1;
+                        }
+                    }
+                }
+            }
+        }
+        if (changed && __builtin_amdgcn_read_exec() && __any(dec) && (tid % warpSize) == 0) atomicOr(changed, 1u);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int r = m0 + row_of(i);
@@ -479,6 +631,148 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int c = tx + 16 * j;
+            if (r < s && c < s) D[(int64_t)r * ld + c] = x[i][j];
+        }
+    }
+}
+
+// The same blocked closure for a workgroup of 512 lanes (two waves per SIMD,
+// so one wave's LDS reads and barriers hide behind the other's folds).
+// Lane (ty, tx), ty < 16, tx < 32, owns the 8 x 4 elements at rows ty + 16*i
+// and columns tx + 32*j; band r is register rows {2r, 2r+1} and register
+// column r of every lane.  Phases, LDS layout (R / Cc, 34 KB) and results
+// are those of close_block; with half the elements per lane it needs 126
+// VGPRs instead of 162 and closes a 128 x 128 block in about two thirds of
+// the time.
+constexpr int kCloseWideThreads = 512;
+
+template <class S>
+__device__ __forceinline__ void close_block_wide(typename S::T* __restrict__ D, int64_t ld, int s,
+                                                 typename S::T* lds)
+{
+    using T = typename S::T;
+    using P = typename S::P;
+    T* R = lds;                       // R[kk * kLdR + col]  = X[p0 + kk][col]
+    T* Cc = lds + kBand * kLdR;       // Cc[row * kLdC + kk] = X[row][p0 + kk]
+    const int tid = threadIdx.x;
+    const int tx = tid & 31, ty = tid >> 5;
+
+    T x[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = ty + 16 * i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = tx + 32 * j;
+            x[i][j] = (r < s && c < s) ? D[(int64_t)r * ld + c] : S::inf();
+        }
+    }
+
+    const int rounds = (s + kBand - 1) / kBand;
+#pragma unroll
+    for (int rd = 0; rd < kMaxS / kBand; ++rd) {
+        if (rd >= rounds) break;
+        const int p0 = kBand * rd;
+        const int i0 = 2 * rd;        // band rows are register rows i0, i0 + 1; band column is rd
+        // ---- 0. publish the band
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) R[(ty + 16 * a) * kLdR + tx + 32 * j] = x[i0 + a][j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Cc[(ty + 16 * i) * kLdC + tx] = x[i][rd];
+        __syncthreads();
+        // ---- 1. pivot block: squaring to a fixpoint (at most log2(32) + 1 passes change it)
+        for (int pass = 0; pass < 8; ++pass) {
+            T np[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) np[a] = x[i0 + a][rd];
+#pragma unroll 4
+            for (int kk = 0; kk < kBand; kk += 2) {
+                const P pb = S::pair(R[kk * kLdR + p0 + tx], R[(kk + 1) * kLdR + p0 + tx]);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    np[a] = S::fold(np[a], *reinterpret_cast<const P*>(&R[(ty + 16 * a) * kLdR + p0 + kk]), pb);
+            }
+            const int changed = (np[0] < x[i0][rd]) | (np[1] < x[i0 + 1][rd]);
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                x[i0 + a][rd] = np[a];
+                R[(ty + 16 * a) * kLdR + p0 + tx] = np[a];
+            }
+            if (!__syncthreads_or(changed)) break;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) Cc[(ty + 16 * (i0 + a)) * kLdC + tx] = x[i0 + a][rd];
+        __syncthreads();
+        // ---- 2. panels, from the closed pivot and the pre-update panels
+        T nr[2][4], nc[8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) nr[a][j] = x[i0 + a][j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) nc[i] = x[i][rd];
+#pragma unroll 2
+        for (int kk = 0; kk < kBand; kk += 2) {
+            P pa[8], pb[4];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pa[i] = *reinterpret_cast<const P*>(&Cc[(ty + 16 * i) * kLdC + kk]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                pb[j] = S::pair(R[kk * kLdR + tx + 32 * j], R[(kk + 1) * kLdR + tx + 32 * j]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) nr[a][j] = S::fold(nr[a][j], pa[i0 + a], pb[j]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) nc[i] = S::fold(nc[i], pa[i], pb[rd]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j == rd) continue;
+                x[i0 + a][j] = nr[a][j];
+                R[(ty + 16 * a) * kLdR + tx + 32 * j] = nr[a][j];
+            }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i == i0 || i == i0 + 1) continue;
+            x[i][rd] = nc[i];
+            Cc[(ty + 16 * i) * kLdC + tx] = nc[i];
+        }
+        __syncthreads();
+        // ---- 3. remainder: other rows x other columns (registers only)
+#pragma unroll 2
+        for (int kk = 0; kk < kBand; kk += 2) {
+            P pa[8], pb[4];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pa[i] = *reinterpret_cast<const P*>(&Cc[(ty + 16 * i) * kLdC + kk]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                pb[j] = S::pair(R[kk * kLdR + tx + 32 * j], R[(kk + 1) * kLdR + tx + 32 * j]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i == i0 || i == i0 + 1) continue;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j == rd) continue;
+                    x[i][j] = S::fold(x[i][j], pa[i], pb[j]);
+                }
+            }
+        }
+        __syncthreads();                     // R / Cc are republished next round
+    }
+
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = ty + 16 * i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = tx + 32 * j;
             if (r < s && c < s) D[(int64_t)r * ld + c] = x[i][j];
         }
     }

@@ -7,9 +7,13 @@
 
 namespace apsp {
 
-enum DType : int32_t { I32 = 0, F32 = 1 };
+// I32P16: int32 data whose min-plus products run in capped 16-bit arithmetic
+// (internal; the public dtype stays int32).
+enum DType : int32_t { I32 = 0, F32 = 1, I32P16 = 2 };
 
 constexpr uint32_t kInfI32 = 1u << 30;
+// Cap of the capped 16-bit min-plus mode: stands for "no path below the cap".
+constexpr uint32_t kCap16 = 0x7fffu;
 
 // One min-plus product C <- min(C, A (min,+) B) over a rectangular window.
 // Optional exclusion bands remove a run of tile rows / tile columns from the
@@ -42,11 +46,11 @@ struct GemmGroup {
 enum Tile : int32_t { TILE_128 = 1, TILE_64 = 2 };
 
 struct TileShape { int mt, nt, kt; };
-TileShape tile_shape(int tile);
+TileShape tile_shape(int tile, DType dt = I32);
 
 // Fills tiles/wg fields of every problem and the group total for `tile`.
 // split_target: desired number of workgroups (0 disables split-K).
-void finalize_group(GemmGroup& g, int tile, int split_target);
+void finalize_group(GemmGroup& g, int tile, int split_target, DType dt = I32);
 
 hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, hipStream_t s);
 
@@ -57,6 +61,11 @@ hipError_t launch_closure(DType dt, int kind, void* D, int64_t ld, int32_t s, hi
 // Counts contract violations into *d_count (uint64, pre-zeroed by the kernel
 // launcher on the same stream).
 hipError_t launch_validate(DType dt, const void* D, int64_t n, int64_t ld,
+                           unsigned long long* d_count, hipStream_t st);
+
+// Counts entries of the n x n int32 matrix that are >= thr into *d_count
+// (uint64, zeroed by the caller on the same stream).
+hipError_t launch_count_ge(const uint32_t* D, int64_t n, int64_t ld, uint32_t thr,
                            unsigned long long* d_count, hipStream_t st);
 
 // Fill kernel used instead of hipMemsetAsync for small device counters.

@@ -16,6 +16,11 @@
 //        Saturation is free: sums stay <= 2^31 in u32 and the accumulator
 //        starts at C <= INF, so min() never lets anything above INF through.
 // fp32:  two v_add_f32 (one IEEE rounding each) and one v_min3_f32.
+// int32, capped 16-bit mode: four steps per 64-bit LDS word, values capped at
+//        2^15 - 1 while staged; one 64-bit add and two v_pk_min_u16 per
+//        4 terms (SemU16).  Used by the solvers' PACKED16 option, which
+//        checks the result and redoes the solve in int32 when any entry
+//        reached the cap.
 //
 // Workgroup order: the flat grid is first redistributed so that consecutive
 // tile indices land on the same XCD (the dispatcher deals workgroups to the
@@ -32,6 +37,7 @@ namespace {
 using dev::Cfg;
 using dev::SemF32;
 using dev::SemI32;
+using dev::SemU16;
 
 template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC>
 __global__ __launch_bounds__((MT / TM) * (NT / TN))
@@ -39,8 +45,8 @@ void k_minplus(const GemmGroup G, uint32_t* __restrict__ changed)
 {
     using T = typename S::T;
     using P = typename S::P;
-    __shared__ P As[2][KT / 2][MT + 2];
-    __shared__ P Bs[2][KT / 2][NT + 2];
+    __shared__ P As[2][KT / S::KPACK][MT + 2];
+    __shared__ P Bs[2][KT / S::KPACK][NT + 2];
 
     // ---- which problem / split / tile this workgroup owns
     const int bid = dev::xcd_remap(blockIdx.x, gridDim.x);
@@ -95,24 +101,36 @@ hipError_t launch_cfg(const GemmGroup& g, uint32_t* changed, hipStream_t st)
     return hipGetLastError();
 }
 
+// Reduction slice per tile shape: 16 steps for 128-tiles, 32 for 64-tiles;
+// the 16-bit mode (four steps per word) keeps 16 for 128-tiles, where its
+// staging registers then stay few enough for three waves per SIMD, and
+// takes 64 for 64-tiles.
 template <class S>
 hipError_t launch_sem(int tile, const GemmGroup& g, uint32_t* changed, hipStream_t st)
 {
-    if (tile == TILE_64) return launch_cfg<S, 64, 64, 32, 4, 4>(g, changed, st);
+    constexpr int X = S::KPACK / 2;
+    if (tile == TILE_64) return launch_cfg<S, 64, 64, 32 * X, 4, 4>(g, changed, st);
     return launch_cfg<S, 128, 128, 16, 8, 8>(g, changed, st);
+}
+
+hipError_t launch_dtype(DType dt, int tile, const GemmGroup& g, uint32_t* changed, hipStream_t st)
+{
+    if (dt == I32) return launch_sem<SemI32>(tile, g, changed, st);
+    if (dt == I32P16) return launch_sem<SemU16>(tile, g, changed, st);
+    return launch_sem<SemF32>(tile, g, changed, st);
 }
 
 }  // namespace
 
-TileShape tile_shape(int tile)
+TileShape tile_shape(int tile, DType dt)
 {
-    if (tile == TILE_64) return {64, 64, 32};
+    if (tile == TILE_64) return {64, 64, dt == I32P16 ? 64 : 32};
     return {128, 128, 16};
 }
 
-void finalize_group(GemmGroup& g, int tile, int split_target)
+void finalize_group(GemmGroup& g, int tile, int split_target, DType dt)
 {
-    const TileShape ts = tile_shape(tile);
+    const TileShape ts = tile_shape(tile, dt);
     int64_t base_tiles = 0;
     for (int i = 0; i < g.count; ++i) {
         GemmProblem& p = g.p[i];
@@ -150,8 +168,7 @@ void finalize_group(GemmGroup& g, int tile, int split_target)
 hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, hipStream_t st)
 {
     if (g.total_wgs <= 0) return hipSuccess;
-    if (dt == I32) return launch_sem<SemI32>(tile, g, nullptr, st);
-    return launch_sem<SemF32>(tile, g, nullptr, st);
+    return launch_dtype(dt, tile, g, nullptr, st);
 }
 
 hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld,
@@ -163,10 +180,9 @@ hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld
     p.A = D; p.B = D; p.C = D;
     p.lda = p.ldb = p.ldc = ld;
     p.M = p.N = p.K = (int32_t)n;
-    finalize_group(g, tile, 0);
+    finalize_group(g, tile, 0, dt);
     if (g.total_wgs <= 0) return hipSuccess;
-    if (dt == I32) return launch_sem<SemI32>(tile, g, d_changed, st);
-    return launch_sem<SemF32>(tile, g, d_changed, st);
+    return launch_dtype(dt, tile, g, d_changed, st);
 }
 
 }  // namespace apsp

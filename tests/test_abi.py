@@ -156,3 +156,26 @@ def test_reconstruct_path_host_logic(native):
     assert native.reconstruct_path(row, 0, 0) == [0]
     with pytest.raises(ValueError):
         native.reconstruct_path(np.array([-1, 2, 1], dtype=np.int32), 0, 2)
+
+
+def test_packed16_option_is_checked_before_any_device_call(native):
+    L = native.lib()
+    fake = ctypes.c_void_p(0x1000)
+    o = native.make_opts(packed16=True)
+    # fp32 data: unsupported, for every solver
+    for name in ("apsp_fw", "apsp_rkleene", "apsp_square", "apsp_solve"):
+        assert _call_square(native, name, None, 1, 8, fake, 8, o) == native.APSP_E_UNSUPPORTED, name
+        assert "int32" in native.last_error()
+    # int32 data: accepted by the solvers (then the missing context is reported)
+    for name in ("apsp_fw", "apsp_rkleene", "apsp_square", "apsp_solve"):
+        assert _call_square(native, name, None, 0, 8, fake, 8, o) == native.APSP_E_ARG, name
+        assert "context" in native.last_error()
+    # entry points without the int32 redo reject it
+    assert _call_square(native, "apsp_closure", None, 0, 8, fake, 8, o) == native.APSP_E_UNSUPPORTED
+    A, B, C = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
+    assert L.minplus_gemm(None, 0, 2, 2, 2, A, 2, B, 2, C, 2, ctypes.byref(o), None) == native.APSP_E_UNSUPPORTED
+    assert "minplus_gemm" in native.last_error()
+    n = (ctypes.c_int32 * 1)(4)
+    assert L.apsp_batched(None, 0, 1, fake, fake, fake, n, ctypes.byref(o), None) == native.APSP_E_UNSUPPORTED
+    runs, redone = ctypes.c_int64(), ctypes.c_int64()
+    assert L.apsp_packed16_counts(None, ctypes.byref(runs), ctypes.byref(redone)) == native.APSP_E_ARG
