@@ -241,8 +241,9 @@ apsp_status_t apsp_validate(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
 
 /*
  * Candidate plans.  A fixed table of (algorithm, round width / leaf size,
- * tile, closure, cutover) choices indexed 0..apsp_candidate_count()-1; the
- * autotuner times every one of them and the cost model scores them.
+ * tile, closure, cutover, flags) choices indexed 0..apsp_candidate_count()-1;
+ * the autotuner times every one of them and the cost model scores them.
+ * Some carry APSP_FLAG_PACKED16 (int32 data only).
  */
 int32_t apsp_candidate_count(void);
 apsp_status_t apsp_candidate(int32_t index, apsp_opts_t *out);
@@ -291,12 +292,13 @@ apsp_status_t apsp_costmodel_forward(apsp_ctx_t *ctx, const float *d_X, int32_t 
 apsp_status_t apsp_costmodel_predict(apsp_ctx_t *ctx, const float *d_X, int32_t rows, int32_t *d_choice,
                                      void *stream);
 
-/* Plan for one problem (synchronous): the cost model's argmin when a model
- * with K = apsp_candidate_count() is loaded, else a size rule (blocked FW up
- * to n = 4096, R-Kleene with a 4096 FW cutover above).  *h_choice (may be NULL) gets the candidate
- * index, or -1 for the size rule. */
-apsp_status_t apsp_plan(apsp_ctx_t *ctx, int64_t n, double density, int32_t batch, int32_t connected,
-                        apsp_opts_t *out, int32_t *h_choice);
+/* Plan for one problem of `dtype` (synchronous): the cost model's argmin
+ * over the candidates that dtype can run (fp32 skips the APSP_FLAG_PACKED16
+ * ones) when a model with K = apsp_candidate_count() is loaded, else a size
+ * rule (blocked FW up to n = 4096, R-Kleene with a 4096 FW cutover above).
+ * *h_choice (may be NULL) gets the candidate index, or -1 for the size rule. */
+apsp_status_t apsp_plan(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n, double density, int32_t batch,
+                        int32_t connected, apsp_opts_t *out, int32_t *h_choice);
 
 /*
  * Kernel timing for measurement tools (not needed to compute anything).

@@ -120,7 +120,7 @@ def lib() -> ctypes.CDLL:
             L.apsp_costmodel_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
             L.apsp_costmodel_forward.argtypes = [vp, vp, i32, vp, vp]
             L.apsp_costmodel_predict.argtypes = [vp, vp, i32, vp, vp]
-            L.apsp_plan.argtypes = [vp, i64, ctypes.c_double, i32, i32, P(Opts), P(i32)]
+            L.apsp_plan.argtypes = [vp, i32, i64, ctypes.c_double, i32, i32, P(Opts), P(i32)]
             for name in EXPORTS:
                 if name not in ("apsp_last_error", "apsp_version"):
                     getattr(L, name).restype = i32
@@ -406,10 +406,13 @@ def apsp_costmodel_predict(X, choice, stream=None):
     return choice
 
 
-def apsp_plan(n: int, density: float, batch: int = 1, connected: bool = True, device: int | None = None):
-    """Returns (Opts, candidate index or -1 for the built-in size rule)."""
+def apsp_plan(n: int, density: float, batch: int = 1, connected: bool = True, dtype: str = "int32",
+              device: int | None = None):
+    """Returns (Opts, candidate index or -1 for the built-in size rule) for a
+    problem of `dtype` ("int32" or "float32")."""
     o = Opts()
     ch = ctypes.c_int32(-1)
-    _check(lib().apsp_plan(context(device), n, float(density), batch, 1 if connected else 0,
+    dt = {"int32": 0, "float32": 1}[dtype]
+    _check(lib().apsp_plan(context(device), dt, n, float(density), batch, 1 if connected else 0,
                            ctypes.byref(o), ctypes.byref(ch)))
     return o, int(ch.value)

@@ -87,7 +87,8 @@ def candidate_table(apsp):
     out = []
     for i in range(apsp.apsp_candidate_count()):
         o = apsp.apsp_candidate(i)
-        out.append({"algo": o.algo, "block": o.block, "tile": o.tile, "closure": o.closure, "cutover": o.cutover})
+        out.append({"algo": o.algo, "block": o.block, "tile": o.tile, "closure": o.closure, "cutover": o.cutover,
+                    "flags": o.flags})
     return out
 
 
@@ -229,9 +230,9 @@ def size_rule(n, cands):
     """Index of the candidate the library's size rule runs (blocked FW up to
     n = 4096, R-Kleene with a 4096 FW cutover above)."""
     if n <= 4096:
-        want = {"algo": 1, "block": 128, "tile": 0, "closure": 1, "cutover": 0}
+        want = {"algo": 1, "block": 128, "tile": 0, "closure": 1, "cutover": 0, "flags": 0}
     else:
-        want = {"algo": 2, "block": 128, "tile": 0, "closure": 1, "cutover": 4096}
+        want = {"algo": 2, "block": 128, "tile": 0, "closure": 1, "cutover": 4096, "flags": 0}
     for i, c in enumerate(cands):
         if c == want:
             return i

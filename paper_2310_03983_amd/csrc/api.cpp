@@ -523,18 +523,24 @@ apsp_status_t reject_packed16(const apsp_opts_t* o, const char* who)
 }
 
 // Candidate plans scored by the cost model and timed by the autotuner.
+// The last three run their products in capped 16-bit arithmetic (int32 only;
+// same result, faster when every distance is below the cap, slower when the
+// int32 redo runs).
 struct Candidate {
-    int32_t algo, block, tile, closure, cutover;
+    int32_t algo, block, tile, closure, cutover, flags;
 };
 const Candidate kCandidates[] = {
-    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},        // size rule, n <= 4096
-    {APSP_ALGO_FW, 64, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
-    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0},
-    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 4096},  // size rule, n > 4096
-    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 1024},
-    {APSP_ALGO_RKLEENE, 128, APSP_TILE_64, APSP_CLOSURE_KLOOP, 0},
-    {APSP_ALGO_SQUARE, 0, APSP_TILE_AUTO, APSP_CLOSURE_AUTO, 0},
-    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_SQUARE, 0},
+    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0, 0},        // size rule, n <= 4096
+    {APSP_ALGO_FW, 64, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0, 0},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0, 0},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 4096, 0},  // size rule, n > 4096
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 1024, 0},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_64, APSP_CLOSURE_KLOOP, 0, 0},
+    {APSP_ALGO_SQUARE, 0, APSP_TILE_AUTO, APSP_CLOSURE_AUTO, 0, 0},
+    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_SQUARE, 0, 0},
+    {APSP_ALGO_FW, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 0, APSP_FLAG_PACKED16},
+    {APSP_ALGO_RKLEENE, 128, APSP_TILE_AUTO, APSP_CLOSURE_KLOOP, 4096, APSP_FLAG_PACKED16},
+    {APSP_ALGO_SQUARE, 0, APSP_TILE_AUTO, APSP_CLOSURE_AUTO, 0, APSP_FLAG_PACKED16},
 };
 constexpr int32_t kNumCandidates = (int32_t)(sizeof(kCandidates) / sizeof(kCandidates[0]));
 constexpr int32_t kCmMaxRows = 4096;
@@ -1087,6 +1093,7 @@ apsp_status_t apsp_candidate(int32_t index, apsp_opts_t* out)
     out->tile = c.tile;
     out->closure = c.closure;
     out->cutover = c.cutover;
+    out->flags = c.flags;
     return APSP_OK;
 }
 
@@ -1245,10 +1252,11 @@ apsp_status_t apsp_costmodel_predict(apsp_ctx_t* ctx, const float* X, int32_t ro
     return APSP_OK;
 }
 
-apsp_status_t apsp_plan(apsp_ctx_t* ctx, int64_t n, double density, int32_t batch, int32_t connected,
-                        apsp_opts_t* out, int32_t* h_choice)
+apsp_status_t apsp_plan(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, double density, int32_t batch,
+                        int32_t connected, apsp_opts_t* out, int32_t* h_choice)
 {
     apsp_status_t rc;
+    if ((rc = check_dtype(dt))) return rc;
     if (!out) return fail(APSP_E_ARG, "output is NULL");
     if (n < 0 || batch < 1 || density < 0.0) return fail(APSP_E_ARG, "bad plan features");
     if ((rc = check_ctx(ctx))) return rc;
@@ -1263,11 +1271,15 @@ apsp_status_t apsp_plan(apsp_ctx_t* ctx, int64_t n, double density, int32_t batc
                   (float)std::log10(std::max(density, 1e-9)), (float)std::log2((double)batch),
                   connected ? 1.f : 0.f};
     HIP_TRY(hipMemcpy(ctx->cm_io, x, sizeof x, hipMemcpyHostToDevice), "plan features upload");
-    rc = apsp_costmodel_predict(ctx, ctx->cm_io, 1, reinterpret_cast<int32_t*>(ctx->cm_io + 4), nullptr);
-    if (rc) return rc;
-    int32_t choice = 0;
-    HIP_TRY(hipMemcpy(&choice, ctx->cm_io + 4, sizeof choice, hipMemcpyDeviceToHost), "plan choice download");
-    if (choice < 0 || choice >= kNumCandidates) return fail(APSP_E_STATE, "model chose %d", choice);
+    if ((rc = apsp_costmodel_forward(ctx, ctx->cm_io, 1, ctx->cm_io + 4, nullptr))) return rc;
+    float pred[kNumCandidates];
+    HIP_TRY(hipMemcpy(pred, ctx->cm_io + 4, sizeof pred, hipMemcpyDeviceToHost), "plan scores download");
+    // first minimum among the candidates this dtype can run
+    int32_t choice = -1;
+    for (int32_t i = 0; i < kNumCandidates; ++i) {
+        if (dt != APSP_I32 && (kCandidates[i].flags & APSP_FLAG_PACKED16)) continue;
+        if (choice < 0 || pred[i] < pred[choice]) choice = i;
+    }
     if (h_choice) *h_choice = choice;
     return apsp_candidate(choice, out);
 }

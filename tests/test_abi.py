@@ -129,8 +129,10 @@ def test_candidate_table(native):
     for i in range(n):
         o = native.apsp_candidate(i)
         assert o.algo in (1, 2, 3) and o.block in (0, 64, 128)
+        assert o.flags in (0, native.FLAG_PACKED16)
         algos.add(o.algo)
     assert algos == {1, 2, 3}
+    assert any(native.apsp_candidate(i).flags == native.FLAG_PACKED16 for i in range(n))
     with pytest.raises(native.ApspError):
         native.apsp_candidate(n)
 

@@ -138,7 +138,34 @@ def test_plan_uses_model_only_when_it_matches_the_candidates(native, dev):
     o, ch = native.apsp_plan(4096, 0.01)
     assert 0 <= ch < Kc
     ref = native.apsp_candidate(ch)
-    assert (o.algo, o.block, o.tile, o.closure, o.cutover) == (ref.algo, ref.block, ref.tile, ref.closure, ref.cutover)
+    assert (o.algo, o.block, o.tile, o.closure, o.cutover, o.flags) == \
+        (ref.algo, ref.block, ref.tile, ref.closure, ref.cutover, ref.flags)
+
+
+def test_plan_for_fp32_skips_packed_candidates(native, dev):
+    import json
+    import os
+    from paper_2310_03983_amd import autotune
+    model = json.load(open(os.path.join(os.path.dirname(autotune.__file__), "data", "costmodel_mlp.json")))
+    autotune.install(model)
+    Kc = native.apsp_candidate_count()
+    packed = {i for i in range(Kc) if native.apsp_candidate(i).flags & native.FLAG_PACKED16}
+    assert packed
+    # large dense graphs: the int32 plan is a packed candidate (the sweep's winner there)
+    o, ch = native.apsp_plan(16384, 0.01)
+    assert ch in packed
+    for n, dens in ((16384, 0.01), (2048, 0.3), (300, 0.01), (8192, 0.001)):
+        X = torch.tensor([[np.log2(n), np.log10(dens), 0.0, 1.0]], dtype=torch.float32, device=dev)
+        out = torch.empty((1, Kc), dtype=torch.float32, device=dev)
+        native.apsp_costmodel_forward(X, out)
+        torch.cuda.synchronize()
+        scores = out.cpu().numpy()[0]
+        allowed = [i for i in range(Kc) if i not in packed]
+        o, ch = native.apsp_plan(n, dens, dtype="float32")
+        assert ch == allowed[int(np.argmin(scores[allowed]))]
+        assert not (o.flags & native.FLAG_PACKED16)
+        o, ch = native.apsp_plan(n, dens)
+        assert ch == int(np.argmin(scores))
 
 
 def test_trained_model_gain_on_held_out_graphs(native, dev):

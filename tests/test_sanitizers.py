@@ -38,7 +38,8 @@ DRIVER = textwrap.dedent(r"""
         int32_t sizes[2] = {3, 2000};
         EXPECT(apsp_batched(NULL, APSP_I32, 2, fake, fake, fake, sizes, NULL, NULL) == APSP_E_UNSUPPORTED);
         EXPECT(apsp_batched(NULL, APSP_I32, -1, fake, fake, fake, sizes, NULL, NULL) == APSP_E_ARG);
-        EXPECT(apsp_plan(NULL, 100, 0.1, 1, 1, NULL, NULL) == APSP_E_ARG);
+        EXPECT(apsp_plan(NULL, APSP_I32, 100, 0.1, 1, 1, NULL, NULL) == APSP_E_ARG);
+        EXPECT(apsp_plan(NULL, (apsp_dtype_t)9, 100, 0.1, 1, 1, NULL, NULL) == APSP_E_ARG);
         EXPECT(apsp_candidate(-1, &o) == APSP_E_ARG);
         for (int i = 0; i < apsp_candidate_count(); ++i) EXPECT(apsp_candidate(i, &o) == APSP_OK);
         EXPECT(apsp_costmodel_init(NULL, 0, 1) == APSP_E_ARG);
