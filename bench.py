@@ -34,9 +34,9 @@ METRIC = "APSP n³ updates/s & % VALU roofline at n=16384 int32; batched graphs/
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # Algorithmic operations (an add and a min per term) done by one lane-instruction
 # of the fold: int32 -- one v_lshl_add_u64 forms two sums, one v_min3_u32 takes
-# two minima: 2; capped 16-bit -- one 64-bit add forms four sums and two
-# v_pk_min_u16 take four minima: 8 ops in 3 instructions.
-OPS_PER_INSTR = {False: 2.0, True: 8.0 / 3.0}
+# two minima: 2; capped 16-bit -- one 64-bit add forms four sums and one
+# v_pk_minimum3_f16 takes four minima: 4.
+OPS_PER_INSTR = {False: 2.0, True: 4.0}
 
 
 def parse():
@@ -103,7 +103,7 @@ def bench_packed16(torch, apsp, Wd, n, cutover):
             "solves": runs1 - runs0, "int32_redone": redone1 - redone0,
             "bit_identical_to_int32": same,
             "minplus128_terms_per_s": k["terms"] / (k["ms"] / 1e3) if k["ms"] else None,
-            "note": "int32 in and out; products fold 4 terms in 3 instructions (capped 16-bit); "
+            "note": "int32 in and out; products fold 4 terms in 2 instructions (capped 16-bit); "
                     "exact, checked by counting capped entries after the solve"}
 
 
@@ -307,8 +307,8 @@ def main():
             "peak_lane_instr": VALU_PEAK_OPS / 1e12,
             "ops_per_lane_instr": OPS_PER_INSTR[args.packed16],
             "note": ("achieved: 2 algorithmic ops per min-plus term (add + min); peak: 39.32e12 VALU "
-                     "lane-instructions/s x the ops one lane-instruction of the fold performs (one 64-bit add "
-                     "forms four 16-bit sums, two v_pk_min_u16 take four minima: 8 ops in 3 instructions)")
+                     "lane-instructions/s x the 4 ops one lane-instruction of the fold performs (one 64-bit add "
+                     "forms four 16-bit sums, one v_pk_minimum3_f16 takes four minima)")
                     if args.packed16 else
                     ("achieved: 2 algorithmic ops per min-plus term (add + min); peak: 39.32e12 VALU "
                      "lane-instructions/s x the 2 ops one lane-instruction of the fold performs (one 64-bit add "

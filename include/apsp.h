@@ -168,15 +168,16 @@ apsp_status_t apsp_square(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  * APSP_FLAG_PACKED16 (int32 only; other dtypes: APSP_E_UNSUPPORTED, and
  * minplus_gemm / apsp_closure / apsp_batched reject it).  The min-plus
  * products of apsp_fw / apsp_rkleene / apsp_square stage every value capped
- * at 2^15 - 1 and fold four reduction steps with one 64-bit add and two
- * packed 16-bit minima, a third fewer instructions per term than int32; the
- * matrix in memory stays int32.  Capping commutes with min and +, so an
- * entry below the cap is exact.  After the solve one pass counts entries
- * >= 2^15 - 1 and reads the count back (the call then returns with `stream`
- * synchronised); if there are any, the int32 solver runs once more on the
- * result, which yields the exact int32 closure.  The output is therefore
- * identical to the int32 solver's in every case; the mode pays off when all
- * distances are below 32767 and every vertex reaches every other.
+ * at 14847 as a 16-bit pattern and fold four reduction steps with one 64-bit
+ * add and one packed three-way minimum, half the instructions per term of
+ * int32; the matrix in memory stays int32.  Capping commutes with min and +,
+ * so an entry below the cap is exact.  After the solve one pass counts
+ * entries >= 14847 and reads the count back (the call then returns with
+ * `stream` synchronised); if there are any, the int32 solver runs once more
+ * on the result, which yields the exact int32 closure.  The output is
+ * therefore identical to the int32 solver's in every case; the mode pays
+ * off when all distances are below 14847 and every vertex reaches every
+ * other.
  * apsp_packed16_counts reports how many solves used the mode and how many
  * of them were redone.
  */

@@ -25,7 +25,7 @@ CLOSURE = {"auto": 0, "kloop": 1, "square": 2}
 TILE = {"auto": 0, 128: 1, 64: 2}
 FLAG_NO_SPLITK, FLAG_BATCH_NO_GRAPH, FLAG_BATCH_PER_GRAPH, FLAG_NO_LOOKAHEAD, FLAG_BATCH_PERSISTENT = 1, 2, 4, 8, 16
 FLAG_PACKED16 = 32
-CAP16 = 0x7FFF
+CAP16 = 0x39FF    # 14847: cap of the APSP_FLAG_PACKED16 products
 
 # every symbol include/apsp.h declares
 EXPORTS = [

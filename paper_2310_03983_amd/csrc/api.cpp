@@ -486,7 +486,7 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
 }
 
 // APSP_FLAG_PACKED16 epilogue.  The products ran in arithmetic capped at
-// 2^15 - 1; capping commutes with min and +, so every stored value below the
+// kCap16 = 14847; capping commutes with min and +, so every stored value below the
 // cap is an exact distance, and every stored value is the length of a real
 // walk (or INF) and no larger than the input entry.  If no entry reached the
 // cap the result is therefore the int32 result.  Otherwise the int32 solver

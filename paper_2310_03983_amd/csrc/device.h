@@ -64,56 +64,45 @@ struct SemF32 {
 };
 
 // int32 distances folded in capped 16-bit arithmetic.  Every value v is
-// staged as min(v, kCap16), kCap16 = 2^15 - 1 standing for "no path"; four
-// consecutive reduction steps share one 64-bit LDS word.  One 64-bit add then
-// forms four 16-bit sums (each <= 2 kCap16 < 2^16, so no carry crosses a
-// lane) and two v_pk_min_u16 fold them into an accumulator of two 16-bit
-// partial minima (even / odd steps): 3 instructions per 4 terms.
-// Capping commutes with min and with saturating addition,
-//   min(a + b, cap) = min(min(a, cap) + min(b, cap), cap)   (a, b >= 0),
-// so the folded value is exactly min(true value, kCap16).  acc_value widens
-// kCap16 back to INF; the product's epilogue keeps the old C entry whenever
+// staged as the 16-bit pattern min(v, kCap16) + 0x400, kCap16 = 14847
+// standing for "no path"; four consecutive reduction steps share one 64-bit
+// LDS word.  One 64-bit add forms the four sums (each at most
+// 2 kCap16 + 0x800 = 0x7bfe, so no carry crosses a lane) and one
+// v_pk_minimum3_f16 folds them into an accumulator of two 16-bit partial
+// minima (even / odd steps): 2 instructions per 4 terms.  The minimum is an
+// fp16 one applied to integer patterns: every pattern lies in
+// [0x400, 0x7bff], the positive normal binary16 numbers, whose order is the
+// order of their bit patterns (the offset keeps subnormals, and any flushing
+// of them, out of play).  Sums and accumulators carry the offset 0x800.
+// Capping commutes with min and with addition of non-negative values,
+//   min(a + b, cap) = min(min(a, cap) + min(b, cap), cap),
+// so the folded value is exactly min(true value, kCap16).  acc_value widens a
+// capped value to INF; the product's epilogue keeps the old C entry whenever
 // that is smaller (a capped result says only "not below kCap16").
-struct SemU16 {
+struct SemP16 {
     using T = uint32_t;
     using P = uint64_t;
     using A = uint32_t;
     static constexpr int KPACK = 4;
     static constexpr uint32_t kCap16 = apsp::kCap16;
+    static constexpr uint32_t kOff = 0x400u;   // smallest positive normal binary16 pattern
     static __device__ __forceinline__ T inf() { return kInfI32; }
-    static __device__ __forceinline__ uint32_t narrow(T v) { return min(v, kCap16); }
+    static __device__ __forceinline__ uint32_t pattern(T v) { return min(v, kCap16) + kOff; }
     static __device__ __forceinline__ P quad(T x0, T x1, T x2, T x3) {
-        const uint32_t lo = narrow(x0) | (narrow(x1) << 16);
-        const uint32_t hi = narrow(x2) | (narrow(x3) << 16);
+        const uint32_t lo = pattern(x0) | (pattern(x1) << 16);
+        const uint32_t hi = pattern(x2) | (pattern(x3) << 16);
         return ((P)hi << 32) | (P)lo;
     }
-    static __device__ __forceinline__ A acc_from(T c) { return narrow(c) * 0x10001u; }
+    static __device__ __forceinline__ A acc_from(T c) { return (min(c, kCap16) + 2 * kOff) * 0x10001u; }
     static __device__ __forceinline__ T acc_value(A a) {
-        const uint32_t r = min(a & 0xffffu, a >> 16);
+        const uint32_t r = min(a & 0xffffu, a >> 16) - 2 * kOff;
         return r < kCap16 ? r : kInfI32;
     }
-    using U2 = unsigned short __attribute__((ext_vector_type(2)));
     static __device__ __forceinline__ A fold(A acc, P a, P b) {
         const P s = a + b;
-        const U2 lo = __builtin_bit_cast(U2, (uint32_t)s);
-        const U2 hi = __builtin_bit_cast(U2, (uint32_t)(s >> 32));
-        const U2 m = __builtin_elementwise_min(lo, hi);
-        return __builtin_bit_cast(A, __builtin_elementwise_min(__builtin_bit_cast(U2, acc), m));
-    }
-    // Two outputs sharing the A operand, interleaved so that no packed
-    // result is read by the very next instruction: the compiler pads such
-    // back-to-back packed dependences with a wait state, and left to itself
-    // (under register pressure) it chains every fold that way.  The
-    // accumulators written here are next read a whole register tile later.
-    static __device__ __forceinline__ void fold2(A& acc0, A& acc1, P a, P b0, P b1) {
-        const P s0 = a + b0, s1 = a + b1;
-        uint32_t m0, m1;
-        asm("v_pk_min_u16 %0, %4, %5\n\t"
-            "v_pk_min_u16 %1, %6, %7\n\t"
-            "v_pk_min_u16 %2, %2, %0\n\t"
-            "v_pk_min_u16 %3, %3, %1"
-            : "=&v"(m0), "=&v"(m1), "+v"(acc0), "+v"(acc1)
-            : "v"((uint32_t)s0), "v"((uint32_t)(s0 >> 32)), "v"((uint32_t)s1), "v"((uint32_t)(s1 >> 32)));
+        A r;
+        asm("v_pk_minimum3_f16 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"((uint32_t)s), "v"((uint32_t)(s >> 32)));
+        return r;
     }
     static __device__ __forceinline__ void atomic_min(T* p, T v) { atomicMin(p, v); }
 };
@@ -352,18 +341,11 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
                     b[2 * g] = v.x;
                     b[2 * g + 1] = v.y;
                 }
-                if constexpr (KPACK == 4) {
 #pragma unroll
-                    for (int i = 0; i < TM; ++i)
+                for (int i = 0; i < TM; ++i)
 #pragma unroll
-                        for (int j = 0; j < TN; j += 2) S::fold2(acc[i][j], acc[i][j + 1], a[i], b[j], b[j + 1]);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
-                }
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
             }
             if (s + 1 < nslices) store_slice(cur ^ 1);
             __syncthreads();

@@ -12,8 +12,9 @@ namespace apsp {
 enum DType : int32_t { I32 = 0, F32 = 1, I32P16 = 2 };
 
 constexpr uint32_t kInfI32 = 1u << 30;
-// Cap of the capped 16-bit min-plus mode: stands for "no path below the cap".
-constexpr uint32_t kCap16 = 0x7fffu;
+// Cap of the capped 16-bit min-plus mode: stands for "no path below the cap"
+// (two capped values plus the pattern offsets stay a finite binary16 pattern).
+constexpr uint32_t kCap16 = 0x39ffu;
 
 // One min-plus product C <- min(C, A (min,+) B) over a rectangular window.
 // Optional exclusion bands remove a run of tile rows / tile columns from the

@@ -17,8 +17,8 @@
 //        starts at C <= INF, so min() never lets anything above INF through.
 // fp32:  two v_add_f32 (one IEEE rounding each) and one v_min3_f32.
 // int32, capped 16-bit mode: four steps per 64-bit LDS word, values capped at
-//        2^15 - 1 while staged; one 64-bit add and two v_pk_min_u16 per
-//        4 terms (SemU16).  Used by the solvers' PACKED16 option, which
+//        14847 while staged; one 64-bit add and one v_pk_minimum3_f16 per
+//        4 terms (SemP16).  Used by the solvers' PACKED16 option, which
 //        checks the result and redoes the solve in int32 when any entry
 //        reached the cap.
 //
@@ -37,7 +37,7 @@ namespace {
 using dev::Cfg;
 using dev::SemF32;
 using dev::SemI32;
-using dev::SemU16;
+using dev::SemP16;
 
 template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC>
 __global__ __launch_bounds__((MT / TM) * (NT / TN))
@@ -116,7 +116,7 @@ hipError_t launch_sem(int tile, const GemmGroup& g, uint32_t* changed, hipStream
 hipError_t launch_dtype(DType dt, int tile, const GemmGroup& g, uint32_t* changed, hipStream_t st)
 {
     if (dt == I32) return launch_sem<SemI32>(tile, g, changed, st);
-    if (dt == I32P16) return launch_sem<SemU16>(tile, g, changed, st);
+    if (dt == I32P16) return launch_sem<SemP16>(tile, g, changed, st);
     return launch_sem<SemF32>(tile, g, changed, st);
 }
 

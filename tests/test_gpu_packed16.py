@@ -15,7 +15,7 @@ from paper_2310_03983_amd import graphgen as gg
 pytestmark = pytest.mark.gpu
 
 INF = 1 << 30
-CAP = 0x7FFF
+CAP = 0x39FF   # the cap of the packed products (apsp.CAP16)
 FNS = ("fw", "rkleene", "square")
 
 
@@ -146,6 +146,10 @@ def test_packed16_workload_n16384_sampled(native, dev):
     out = host(D[torch.from_numpy(src).to(dev)])
     np.testing.assert_array_equal(out, ref)
     assert after[1] == before[1], "every distance of this workload is below the cap"
+
+
+def test_cap_constant_matches_binding(native):
+    assert native.CAP16 == CAP
 
 
 def test_packed16_rejected_for_f32(native, dev):

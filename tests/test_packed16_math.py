@@ -33,7 +33,7 @@ def random_graph(rng, n, p, hi):
 
 @settings(max_examples=60, deadline=None)
 @given(n=st.integers(1, 24), p=st.floats(0.0, 1.0), hi=st.sampled_from([3, 50, 1000, 40000]),
-       cap=st.sampled_from([1, 7, 100, 0x7FFF]), seed=st.integers(0, 2**31))
+       cap=st.sampled_from([1, 7, 100, 0x39FF, 0x7FFF]), seed=st.integers(0, 2**31))
 def test_capping_commutes_with_the_closure(n, p, hi, cap, seed):
     W = random_graph(np.random.default_rng(seed), n, p, hi)
     true = oracle.fw_i32(W).astype(np.int64)
@@ -54,10 +54,22 @@ def test_redo_from_any_matrix_between_closure_and_input(n, p, hi, seed):
 
 
 def test_a_capped_entry_hides_a_finite_distance():
-    # why the redo is needed: a path of length 3 * 20000 reads as "no path" under the cap
+    # why the redo is needed: a path of length 3 * 9000 reads as "no path" under the cap
     W = np.full((4, 4), INF, np.int32)
     np.fill_diagonal(W, 0)
-    W[0, 1] = W[1, 2] = W[2, 3] = 20000
+    W[0, 1] = W[1, 2] = W[2, 3] = 9000
     true = oracle.fw_i32(W)
-    assert true[0, 3] == 60000
-    assert capped_fw(W, 0x7FFF)[0, 3] == 0x7FFF
+    assert true[0, 3] == 27000
+    assert capped_fw(W, 0x39FF)[0, 3] == 0x39FF
+
+
+def test_binary16_patterns_order_like_integers():
+    # the packed products take integer minima with a binary16 minimum on the
+    # bit patterns: staged values are min(v, cap) + 0x400, sums carry 0x800
+    cap, off = 0x39FF, 0x400
+    pats = np.arange(off, 2 * (cap + off) + 1, dtype=np.uint16)
+    vals = pats.view(np.float16).astype(np.float64)
+    assert np.all(np.isfinite(vals)) and np.all(vals > 0)
+    assert np.all(np.diff(vals) > 0)                      # strictly increasing with the pattern
+    assert 2 * (cap + off) <= 0x7BFF                      # largest sum: the largest finite binary16
+    assert 2 * (cap + off) < 1 << 16                      # no carry into the next 16-bit lane
