@@ -44,7 +44,7 @@ struct apsp_ctx {
     apsp::BatchArgs bargs{};
     // lock-step batched schedule: work items and launch list, captured graph
     std::vector<int4> litems;
-    struct Launch { int phase, offset, count; };
+    struct Launch { int phase, offset, count; bool side; };   // side: on the second stream
     std::vector<Launch> llaunches;
     int4* d_items = nullptr;
     size_t items_bytes = 0;
@@ -859,30 +859,47 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
         std::vector<apsp_ctx::Launch> launches;
         int max_rounds = 0;
         for (int32_t g = 0; g < count; ++g) max_rounds = std::max(max_rounds, (h_sizes[g] + B - 1) / B);
-        for (int r = 0; r < max_rounds; ++r) {
-            for (int phase = 0; phase < 3; ++phase) {
-                const int start = (int)items.size();
-                for (int32_t q = 0; q < count; ++q) {
-                    const int32_t g = order[q];
-                    const int nb = (h_sizes[g] + B - 1) / B;
-                    if (nb <= r || (phase > 0 && nb < 2)) continue;
-                    if (phase == 0) {
-                        items.push_back(make_int4(g, r, 0, 0));
-                    } else if (phase == 1) {
-                        for (int t = 0; t < nb; ++t)
-                            if (t != r) {
-                                items.push_back(make_int4(g, r, t, 0));
-                                items.push_back(make_int4(g, r, t, 1));
-                            }
-                    } else {
-                        for (int ti = 0; ti < nb; ++ti)
-                            for (int tj = 0; tj < nb; ++tj)
-                                if (ti != r && tj != r) items.push_back(make_int4(g, r, ti, tj));
-                    }
-                }
-                const int cnt = (int)items.size() - start;
-                if (cnt > 0) launches.push_back({phase, start, cnt});
+        // Per round r: the pivot closures (round 0 only), the panel tiles,
+        // then the remainder.  When round r+1 exists, its pivot tiles (r+1,
+        // r+1) are updated and closed by one launch (phase 3) on the second
+        // stream while the main stream updates every other remainder tile of
+        // round r on 64 x 64 sub-tiles (phase 4); the next panels wait for
+        // both.  The two streams touch disjoint tiles.
+        auto add = [&](int phase, bool side, auto&& fill) {
+            const int start = (int)items.size();
+            for (int32_t q = 0; q < count; ++q) {
+                const int32_t g = order[q];
+                fill(g, (h_sizes[g] + B - 1) / B);
             }
+            const int cnt = (int)items.size() - start;
+            if (cnt > 0) launches.push_back({phase, start, cnt, side});
+        };
+        for (int r = 0; r < max_rounds; ++r) {
+            if (r == 0)
+                add(0, false, [&](int32_t g, int) { items.push_back(make_int4(g, 0, 0, 0)); });
+            add(1, false, [&](int32_t g, int nb) {
+                if (nb <= r || nb < 2) return;
+                for (int t = 0; t < nb; ++t)
+                    if (t != r) {
+                        items.push_back(make_int4(g, r, t, 0));
+                        items.push_back(make_int4(g, r, t, 1));
+                    }
+            });
+            add(3, true, [&](int32_t g, int nb) {
+                if (r + 1 < nb) items.push_back(make_int4(g, r, r + 1, r + 1));
+            });
+            add(4, false, [&](int32_t g, int nb) {
+                if (nb <= r || nb < 2) return;
+                const int n = h_sizes[g];
+                for (int ti = 0; ti < nb; ++ti)
+                    for (int tj = 0; tj < nb; ++tj) {
+                        if (ti == r || tj == r || (ti == r + 1 && tj == r + 1)) continue;
+                        // 64 x 64 sub-tiles that hold at least one entry
+                        for (int si = 0; si < 2 && ti * B + si * (B / 2) < n; ++si)
+                            for (int sj = 0; sj < 2 && tj * B + sj * (B / 2) < n; ++sj)
+                                items.push_back(make_int4(g, r | (si << 8) | (sj << 9), ti, tj));
+                    }
+            });
         }
         const size_t ib = std::max<size_t>(items.size(), 1) * sizeof(int4);
         if (ib > ctx->items_bytes || !ctx->d_bptrs) {
@@ -932,12 +949,30 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
         // lock-step schedule: point the device record at this call's buffers,
         // then run the launch list (captured once per batch shape)
         auto enqueue = [&](hipStream_t s2) -> hipError_t {
-            for (const auto& L : ctx->llaunches) {
-                hipError_t e = apsp::launch_batch_phase(kdt, L.phase, ctx->d_bptrs, ctx->d_items + L.offset,
-                                                        L.count, s2);
+            hipError_t e = hipSuccess;
+            bool forked = false;
+            auto join = [&]() -> hipError_t {
+                hipError_t je = hipEventRecord(ctx->ev_p, ctx->side);
+                if (je == hipSuccess) je = hipStreamWaitEvent(s2, ctx->ev_p, 0);
+                forked = false;
+                return je;
+            };
+            const bool two = ctx->side && ctx->ev_a && ctx->ev_p;
+            for (const auto& L0 : ctx->llaunches) {
+                apsp_ctx::Launch L = L0;
+                L.side = L.side && two;
+                if (L.side && !forked) {
+                    // the side launches of round r start after its panels
+                    if ((e = hipEventRecord(ctx->ev_a, s2)) != hipSuccess) return e;
+                    if ((e = hipStreamWaitEvent(ctx->side, ctx->ev_a, 0)) != hipSuccess) return e;
+                    forked = true;
+                }
+                if (!L.side && forked && L.phase == 1 && (e = join()) != hipSuccess) return e;
+                e = apsp::launch_batch_phase(kdt, L.phase, ctx->d_bptrs, ctx->d_items + L.offset, L.count,
+                                             L.side ? ctx->side : s2);
                 if (e != hipSuccess) return e;
             }
-            return hipSuccess;
+            return forked ? join() : hipSuccess;
         };
         return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
             HIP_TRY(apsp::launch_batch_ptrs(ctx->d_bptrs, data, d_offsets, d_sizes, st), "batch pointer update");

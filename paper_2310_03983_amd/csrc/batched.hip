@@ -117,13 +117,15 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
 
 // ---------------------------------------------------------------------------
 // Lock-step schedule: every graph advances one 128-wide Floyd-Warshall round
-// per three wide launches -- (1) the pivot closures of all graphs, (2) all
-// their panel tiles, (3) all their remainder tiles -- so a graph's tiles are
-// spread over the whole device instead of one workgroup.  Work items are
-// (graph, round, a, b): closure (a = b = 0); panel tile a of the row (b = 0)
-// or column (b = 1) panel; remainder tile (a, b).  Graphs with n <= 128 are
-// finished by their round-0 closure.  Data pointers are read from a small
-// device record so that a captured launch sequence serves any buffers.
+// per wide launch group -- the pivot closures of all graphs, all their panel
+// tiles, all their remainder tiles -- so a graph's tiles are spread over the
+// whole device instead of one workgroup.  Work items are (graph, round, a,
+// b): closure (a = b = 0); panel tile a of the row (b = 0) or column (b = 1)
+// panel; remainder tile (a, b).  Graphs with n <= 128 are finished by their
+// round-0 closure.  Data pointers are read from a small device record so
+// that a captured launch sequence serves any buffers.  (The host orders the
+// launches so that round r+1's pivot tiles and closures run on a second
+// stream beside the rest of round r's remainder.)
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ __launch_bounds__(dev::kCloseWideThreads) void k_bclose(const BatchPtrs* __restrict__ bp,
@@ -182,6 +184,61 @@ __global__ __launch_bounds__(256) void k_btile(const BatchPtrs* __restrict__ bp,
     dev::mp_tile<S, kB, kB, 16, 8, 8, true>(A, ld, B, ld, C, ld, M, N, 0, 0, 0, bk, false, nullptr, As, Bs);
 }
 
+// Remainder update on 64 x 64 sub-tiles: item (graph, round | si << 8 |
+// sj << 9, a, b) updates rows si*64.. and columns sj*64.. of tile (a, b).
+// Four workgroups per 128-tile fill the device better than one at K = 128;
+// the remainder reads only the pivot's row and column panels, which no
+// remainder item writes, so the split changes no value.
+template <class S>
+__global__ __launch_bounds__(256) void k_bsub(const BatchPtrs* __restrict__ bp, const int4* __restrict__ items)
+{
+    using T = typename S::T;
+    using P = typename S::P;
+    constexpr int MT = 64, KT = 32;
+    __shared__ P As[2][KT / 2][MT + 2];
+    __shared__ P Bs[2][KT / 2][MT + 2];
+    const int4 it = items[blockIdx.x];
+    const int n = bp->sizes[it.x];
+    T* D = static_cast<T*>(bp->data) + bp->offsets[it.x];
+    const int64_t ld = n;
+    const int r = it.y & 0xff;
+    const int k0 = r * kB, bk = min(kB, n - k0);
+    const int r0 = it.z * kB + ((it.y >> 8) & 1) * MT;
+    const int c0 = it.w * kB + ((it.y >> 9) & 1) * MT;
+    dev::mp_tile<S, MT, MT, KT, 4, 4, true>(D + (int64_t)r0 * ld + k0, ld, D + (int64_t)k0 * ld + c0, ld,
+                                           D + (int64_t)r0 * ld + c0, ld, min(MT, n - r0), min(MT, n - c0), 0, 0,
+                                           0, bk, false, nullptr, As, Bs);
+}
+
+// Next pivot of a graph: round r's remainder update of tile (r+1, r+1), then
+// its closure, by one 512-lane workgroup (item (graph, r, r+1, r+1)).  No
+// other remainder tile of round r reads or writes that block, so this runs
+// beside them.
+template <class S>
+__global__ __launch_bounds__(dev::kCloseWideThreads) void k_bpivot(const BatchPtrs* __restrict__ bp,
+                                                                   const int4* __restrict__ items)
+{
+    using T = typename S::T;
+    using P = typename S::P;
+    constexpr int KT = 16;
+    constexpr int kTileBytes = 2 * 2 * (KT / 2) * (kB + 2) * (int)sizeof(P);
+    constexpr int kBytes = kTileBytes > dev::kCloseLdsWords * 4 ? kTileBytes : dev::kCloseLdsWords * 4;
+    __shared__ __attribute__((aligned(16))) char smem[kBytes];
+    auto As = reinterpret_cast<P (*)[KT / 2][kB + 2]>(smem);
+    auto Bs = reinterpret_cast<P (*)[KT / 2][kB + 2]>(smem + kTileBytes / 2);
+    const int4 it = items[blockIdx.x];
+    const int n = bp->sizes[it.x];
+    T* D = static_cast<T*>(bp->data) + bp->offsets[it.x];
+    const int64_t ld = n;
+    const int k0 = it.y * kB, bk = min(kB, n - k0);
+    const int p0 = it.z * kB, w = min(kB, n - p0);
+    T* X = D + (int64_t)p0 * ld + p0;
+    dev::mp_tile<S, kB, kB, KT, 8, 4, true>(D + (int64_t)p0 * ld + k0, ld, D + (int64_t)k0 * ld + p0, ld, X, ld, w,
+                                           w, 0, 0, 0, bk, false, nullptr, As, Bs);
+    __syncthreads();   // the tile's stores are visible to the whole workgroup
+    dev::close_block_wide<S>(X, ld, w, reinterpret_cast<T*>(smem));
+}
+
 __global__ void k_set_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, const int32_t* sizes)
 {
     if (threadIdx.x == 0) {
@@ -223,6 +280,20 @@ hipError_t launch_batch_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, 
 hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const int4* items, int count, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
+    if (phase == 3) {
+        if (dt == I32)
+            hipLaunchKernelGGL(k_bpivot<dev::SemI32>, dim3(count), dim3(dev::kCloseWideThreads), 0, st, bp, items);
+        else
+            hipLaunchKernelGGL(k_bpivot<dev::SemF32>, dim3(count), dim3(dev::kCloseWideThreads), 0, st, bp, items);
+        return hipGetLastError();
+    }
+    if (phase == 4) {
+        if (dt == I32)
+            hipLaunchKernelGGL(k_bsub<dev::SemI32>, dim3(count), dim3(256), 0, st, bp, items);
+        else
+            hipLaunchKernelGGL(k_bsub<dev::SemF32>, dim3(count), dim3(256), 0, st, bp, items);
+        return hipGetLastError();
+    }
     if (phase == 0) {
         if (dt == I32)
             hipLaunchKernelGGL(k_bclose<dev::SemI32>, dim3(count), dim3(dev::kCloseWideThreads), 0, st, bp, items);

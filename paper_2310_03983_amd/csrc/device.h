@@ -292,8 +292,13 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
                 const int p = L / (NT / 2);
                 const int c2 = L % (NT / 2);
                 Pair2<P> v;
-                v.x = S::quad(rb[q][0][0], rb[q][1][0], rb[q][2][0], rb[q][3][0]);
-                v.y = S::quad(rb[q][0][1], rb[q][1][1], rb[q][2][1], rb[q][3][1]);
+                if constexpr (KPACK == 2) {
+                    v.x = S::pack(rb[q][0][0], rb[q][1][0]);
+                    v.y = S::pack(rb[q][0][1], rb[q][1][1]);
+                } else {
+                    v.x = S::quad(rb[q][0][0], rb[q][1][0], rb[q][2][0], rb[q][3][0]);
+                    v.y = S::quad(rb[q][0][1], rb[q][1][1], rb[q][2][1], rb[q][3][1]);
+                }
                 *reinterpret_cast<Pair2<P>*>(&Bs[buf][p][c2 * 2]) = v;
             } else {
                 const int p = L / (NT / 4);

@@ -96,7 +96,10 @@ struct BatchPtrs {
 };
 hipError_t launch_batch_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, const int32_t* sizes,
                              hipStream_t st);
-// phase 0: pivot closures; 1: panel tiles; 2: remainder tiles (items: int4 {graph, round, a, b}).
+// phase 0: pivot closures; 1: panel tiles; 2: remainder tiles; 3: remainder
+// update of the next pivot tile (r+1, r+1) followed by its closure; 4:
+// remainder on 64 x 64 sub-tiles, sub-tile (si, sj) in bits 8 and 9 of the
+// round (items: int4 {graph, round, a, b}).
 hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const int4* items, int count,
                               hipStream_t st);
 int batched_round_width();
