@@ -29,6 +29,13 @@
  * Errors: every call returns an apsp_status_t.  Argument errors are detected
  * before anything is enqueued.  apsp_last_error() returns a thread-local
  * message describing the last failure on the calling thread.
+ *
+ * Contexts: a context owns a second stream and two events (blocked FW's
+ * look-ahead and the batched schedule fork work onto it and join back onto
+ * the caller's stream before returning), small device buffers and cached
+ * batched plans.  It is not thread-safe: use it from one host thread at a
+ * time, and do not let calls through one context run concurrently on
+ * different streams (create one context per concurrent user).
  */
 #ifndef APSP_H
 #define APSP_H
