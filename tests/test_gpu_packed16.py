@@ -157,3 +157,25 @@ def test_packed16_rejected_for_f32(native, dev):
     with pytest.raises(native.ApspError) as e:
         native.apsp_fw(to_dev(F, dev), packed16=True)
     assert e.value.status == native.APSP_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("algo", FNS)
+def test_packed16_random_graphs(native, dev, algo):
+    """Random graphs across the cap: every result bit-identical to the oracle,
+    and the int32 redo runs exactly when some true distance reaches the cap."""
+    from hypothesis import given, settings, HealthCheck, strategies as st
+
+    @settings(max_examples=12, deadline=None, suppress_health_check=list(HealthCheck), derandomize=True)
+    @given(n=st.integers(2, 300), logp=st.floats(-3.0, 0.0), hi=st.sampled_from([5, 200, 3000, 60000]),
+           seed=st.integers(0, 2**31))
+    def check(n, logp, hi, seed):
+        rng = np.random.default_rng(seed)
+        p = 10.0 ** logp
+        W = np.where(rng.random((n, n)) < p, rng.integers(1, hi + 1, (n, n)), INF).astype(np.int32)
+        np.fill_diagonal(W, 0)
+        ref = oracle.fw_i32(W, threads=8)
+        out, runs, redone = run(native, algo, W, dev)
+        np.testing.assert_array_equal(out, ref, err_msg=f"n={n} p={p:.3g} hi={hi}")
+        assert runs == 1 and redone == int((ref >= CAP).any())
+
+    check()
