@@ -107,6 +107,48 @@ def bench_packed16(torch, apsp, Wd, n, cutover):
                     "exact, checked by counting capped entries after the solve"}
 
 
+def bench_small(torch, apsp, gg, dev):
+    """The smaller single-graph configurations: n = 256 (blocked FW, one
+    closure-sized graph), n = 4096 by blocked FW and by R-Kleene, and the
+    last-hop predecessor product at n = 4096 (a dense argmin over n^3 terms)."""
+    out = {}
+
+    def per_solve(fn, W, reps):
+        ins = [W.clone() for _ in range(reps + 2)]
+        t = time_steps(torch, fn, ins, reps, 2)
+        return t / reps
+
+    W256 = torch.from_numpy(gg.SINGLE["n256_p0.1_i32"].make()).to(dev)
+    t = per_solve(apsp.apsp_fw, W256, 200)
+    out["n256_fw_i32"] = {"ms_per_solve": t * 1e3, "updates_per_s": 256 ** 3 / t}
+    W4k = torch.from_numpy(gg.SINGLE["n4096_p0.05_i32"].make()).to(dev)
+    for label, fn in (("n4096_fw_i32", apsp.apsp_fw), ("n4096_rkleene_i32", apsp.apsp_rkleene)):
+        t = per_solve(fn, W4k, 20)
+        out[label] = {"ms_per_solve": t * 1e3, "updates_per_s": 4096 ** 3 / t}
+    D4k = W4k.clone()
+    apsp.apsp_fw(D4k)
+    m = int(torch.count_nonzero(W4k < (1 << 30)).item()) - 4096
+    for method in ("dense", "sparse"):
+        t = time_predecessors(torch, apsp, D4k, W4k, method, 10)
+        out[f"n4096_predecessors_{method}_i32"] = {"ms_per_call": t * 1e3, "edges": m,
+                                                   "candidate_terms_per_s": 4096 * (4096 if method == "dense" else m) / t}
+    return out
+
+
+def time_predecessors(torch, apsp, D, W, method, reps):
+    """Seconds per apsp_predecessors call (the sparse form includes building
+    the edge list and its host synchronisation)."""
+    P = torch.empty_like(D)
+    for _ in range(2):
+        apsp.apsp_predecessors(D, W, P, method=method)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        apsp.apsp_predecessors(D, W, P, method=method)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
 def bench_batched(torch, np, apsp, gg, dev, steps):
     """512 graphs, n log-uniform in [32, 512], p uniform in [0.02, 0.3], int32
     costs 1..100: graphs/s of (a) the lock-step schedule replayed from one
@@ -332,6 +374,17 @@ def main():
             del ins, src
             torch.cuda.empty_cache()
         extras["rkleene_i32_packed16"] = bench_packed16(torch, apsp, Wd, n, args.cutover)
+        extras.update(bench_small(torch, apsp, gg, dev))
+        if Wd.dtype == torch.int32:
+            # last-hop predecessors of the timed graph (sparse form: n * m candidates)
+            Dn = Wd.clone()
+            apsp.apsp_rkleene(Dn, cutover=args.cutover)
+            m = int(torch.count_nonzero(Wd < (1 << 30)).item()) - n
+            t = time_predecessors(torch, apsp, Dn, Wd, "sparse", 3)
+            extras[f"n{n}_predecessors_sparse_i32"] = {"ms_per_call": t * 1e3, "edges": m,
+                                                       "candidate_terms_per_s": n * m / t}
+            del Dn
+            torch.cuda.empty_cache()
         result["extras"] = extras
 
     if not args.no_batched:

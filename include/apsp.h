@@ -207,12 +207,32 @@ apsp_status_t apsp_solve(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  *               -1 when i == j or that minimum is not below INF.
  * When D is the APSP result of W and every off-diagonal cost is positive
  * (the paper's assumption), P[i][j] is the last vertex before j on a shortest
- * i -> j path and following P from j reaches i.  n^3 terms (add, compare,
- * two selects each).  P must not overlap D or W.
+ * i -> j path and following P from j reaches i.  P must not overlap D or W.
+ * Same as apsp_predecessors_ex with APSP_PRED_AUTO.
  */
 apsp_status_t apsp_predecessors(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                                 const void *D, int64_t ldd, const void *W, int64_t ldw,
                                 int32_t *P, int64_t ldp, void *stream);
+
+/* Forms of the predecessor computation (all give the same P). */
+#define APSP_PRED_AUTO   0  /* sparse when W has at most n^2/4 edges and n <= 65535, else dense */
+#define APSP_PRED_DENSE  1  /* one argmin product over every v: n^3 terms (add, compare, two selects) */
+#define APSP_PRED_SPARSE 2  /* only the in-edges of j: n * m candidates; n <= 65535 */
+
+/*
+ * apsp_predecessors with a chosen form.  Only v with W[v][j] < INF can make
+ * D[i][v] (+) W[v][j] fall below INF, so the sparse form takes the argmin
+ * over j's in-edges alone: it lists W's m edges (one pass over W, then one
+ * more to write them; the count is read back, so the call synchronises
+ * `stream`), keeps the context's edge list (8 bytes per edge) for the call,
+ * and folds (value, v) keys with 64-bit LDS atomic minima, ties to the
+ * smallest v.  APSP_PRED_AUTO and APSP_PRED_SPARSE synchronise `stream`;
+ * APSP_PRED_DENSE only enqueues.  Errors: method outside 0..2 is
+ * APSP_E_ARG; APSP_PRED_SPARSE with n > 65535 is APSP_E_UNSUPPORTED.
+ */
+apsp_status_t apsp_predecessors_ex(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
+                                   const void *D, int64_t ldd, const void *W, int64_t ldw,
+                                   int32_t *P, int64_t ldp, int32_t method, void *stream);
 
 /*
  * Many independent graphs, solved together.  `data` holds `count` square
@@ -221,10 +241,12 @@ apsp_status_t apsp_predecessors(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  * the same sizes on the host (used to plan, never dereferenced on device).
  * Every matrix is overwritten with its distances (Sec. 2, Eq. 1 per graph).
  * Default schedule (lock-step): all graphs advance one 128-wide blocked-FW
- * round per three wide launches (pivot closures, panel tiles, remainder
- * tiles of every graph), at most 3 * ceil(max n / 128) launches, captured
- * once per batch shape in a HIP graph and replayed (the buffers of each call
- * are written to a small device record first, so any buffers work).
+ * round per launch group -- the panel tiles of every graph, then the next
+ * round's pivot tiles (updated and closed) on the context's second stream
+ * beside every other remainder tile -- after one launch of all round-0 pivot
+ * closures; at most 3 * ceil(max n / 128) launches, captured once per batch
+ * shape in a HIP graph and replayed (the buffers of each call are written to
+ * a small device record first, so any buffers work).
  * APSP_FLAG_BATCH_PERSISTENT: one persistent kernel whose workgroups take
  * whole graphs, largest first, from an atomic queue (also graph-captured).
  * APSP_FLAG_BATCH_NO_GRAPH launches directly; APSP_FLAG_BATCH_PER_GRAPH

@@ -35,8 +35,9 @@ EXPORTS = [
     "apsp_candidate_count", "apsp_candidate", "apsp_costmodel_init", "apsp_costmodel_set_norm",
     "apsp_costmodel_set_params", "apsp_costmodel_get_params", "apsp_costmodel_train", "apsp_costmodel_grad",
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
-    "apsp_packed16_counts",
+    "apsp_packed16_counts", "apsp_predecessors_ex",
 ]
+PRED = {"auto": 0, "dense": 1, "sparse": 2}
 
 KERNEL_MINPLUS_128, KERNEL_MINPLUS_64, KERNEL_CLOSURE, KERNEL_OTHER = 0, 1, 2, 3
 
@@ -107,6 +108,7 @@ def lib() -> ctypes.CDLL:
             L.apsp_batched.argtypes = [vp, i32, i32, vp, vp, vp, P(i32), P(Opts), vp]
             L.apsp_validate.argtypes = [vp, i32, i64, vp, i64, vp, P(i64)]
             L.apsp_predecessors.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp]
+            L.apsp_predecessors_ex.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, i64, i32, vp]
             L.apsp_profile_enable.argtypes = [vp, i32]
             L.apsp_profile_read.argtypes = [vp, i32, P(KernelStats)]
             f32p = P(ctypes.c_float)
@@ -234,9 +236,10 @@ def apsp_solve(D, opts=None, stream=None, **kw):
     return _square_call("apsp_solve", D, opts, stream, kw)
 
 
-def apsp_predecessors(D, W, P=None, stream=None):
+def apsp_predecessors(D, W, P=None, stream=None, method="auto"):
     """Last-hop predecessor matrix (int32 device tensor) of distances D for
-    costs W (Sec. 2); allocates P when it is not given."""
+    costs W (Sec. 2); allocates P when it is not given.  method: "auto",
+    "dense" or "sparse" (apsp_predecessors_ex)."""
     dt = _dtype(D)
     if W.dtype != D.dtype:
         raise TypeError("D and W must share a dtype")
@@ -250,7 +253,8 @@ def apsp_predecessors(D, W, P=None, stream=None):
     if P.dtype != torch.int32:
         raise TypeError("P must be int32")
     pp, ldp = _matrix(P, "P")
-    _check(lib().apsp_predecessors(context(D.device.index), dt, n, pd, ldd, pw, ldw, pp, ldp, _stream(D, stream)))
+    _check(lib().apsp_predecessors_ex(context(D.device.index), dt, n, pd, ldd, pw, ldw, pp, ldp, PRED[method],
+                                      _stream(D, stream)))
     return P
 
 

@@ -66,6 +66,12 @@ struct apsp_ctx {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
+    int32_t* pred_counts = nullptr; // sparse predecessors: edge counts, offsets, packed edges
+    size_t pred_counts_bytes = 0;
+    int64_t* pred_offsets = nullptr;
+    size_t pred_offsets_bytes = 0;
+    uint64_t* pred_edges = nullptr;
+    size_t pred_edges_bytes = 0;
     int64_t p16_runs = 0;           // solves run with APSP_FLAG_PACKED16
     int64_t p16_redone = 0;         // ... of which were redone in int32
     uint32_t magic = 0x41505350;    // "APSP"
@@ -567,6 +573,27 @@ apsp_status_t check_model(apsp_ctx_t* ctx)
     return APSP_OK;
 }
 
+// Grows a context-held device buffer (synchronising `st` before a free).
+template <class T>
+apsp_status_t grow(T*& p, size_t& have, size_t need, hipStream_t st, const char* what)
+{
+    if (need <= have && p) return APSP_OK;
+    HIP_TRY(hipStreamSynchronize(st), "workspace sync");
+    if (p) hipFree(p);
+    p = nullptr;
+    have = 0;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(need, 256));
+    if (e != hipSuccess) return fail(APSP_E_NOMEM, "%s allocation: %s", what, hipGetErrorString(e));
+    have = std::max<size_t>(need, 256);
+    return APSP_OK;
+}
+
+// Automatic choice of the predecessor form: the sparse one does n * m
+// candidate updates (each an LDS atomic) against the dense kernel's n^3
+// argmin terms, so it is used while the edges are a small share of n^2.
+constexpr double kPredSparseMaxDensity = 0.25;
+constexpr int64_t kPredSparseMaxN = 65535;
+
 }  // namespace
 
 extern "C" {
@@ -638,6 +665,9 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     if (ctx->side) hipStreamDestroy(ctx->side);
     if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
     if (ctx->ev_p) hipEventDestroy(ctx->ev_p);
+    if (ctx->pred_counts) hipFree(ctx->pred_counts);
+    if (ctx->pred_offsets) hipFree(ctx->pred_offsets);
+    if (ctx->pred_edges) hipFree(ctx->pred_edges);
     ctx->magic = 0;
     delete ctx;
     return APSP_OK;
@@ -768,28 +798,80 @@ apsp_status_t apsp_solve(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, i
     }
 }
 
-apsp_status_t apsp_predecessors(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
-                                const void* W, int64_t ldw, int32_t* P, int64_t ldp, void* stream)
+apsp_status_t apsp_predecessors_ex(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
+                                   const void* W, int64_t ldw, int32_t* P, int64_t ldp, int32_t method,
+                                   void* stream)
 {
     apsp_status_t rc;
     if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd)) || (rc = check_square(n, W, ldw)) ||
         (rc = check_square(n, P, ldp)))
         return rc;
     if (n > INT32_MAX / 2) return fail(APSP_E_ARG, "n too large");
+    if (method < APSP_PRED_AUTO || method > APSP_PRED_SPARSE) return fail(APSP_E_ARG, "method = %d", method);
     const size_t pb = span_bytes(n, n, ldp);
     if (n > 0 && (overlaps(P, pb, D, span_bytes(n, n, ldd)) || overlaps(P, pb, W, span_bytes(n, n, ldw))))
         return fail(APSP_E_ARG, "P overlaps D or W");
+    if (method == APSP_PRED_SPARSE && n > kPredSparseMaxN)
+        return fail(APSP_E_UNSUPPORTED, "sparse predecessors need n <= %lld", (long long)kPredSparseMaxN);
     if ((rc = check_ctx(ctx))) return rc;
     if (n == 0) return APSP_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
-    const double terms = (double)n * n * n;
-    return timed(ctx, APSP_KERNEL_OTHER, terms, 12.0 * n * n, st, [&]() -> apsp_status_t {
-        HIP_TRY(apsp::launch_predecessors((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, st),
-                "predecessor launch");
+    auto dense = [&]() -> apsp_status_t {
+        const double terms = (double)n * n * n;
+        return timed(ctx, APSP_KERNEL_OTHER, terms, 12.0 * n * n, st, [&]() -> apsp_status_t {
+            HIP_TRY(apsp::launch_predecessors((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, st),
+                    "predecessor launch");
+            return APSP_OK;
+        });
+    };
+    if (method == APSP_PRED_DENSE || n > kPredSparseMaxN) return dense();
+    // count the edges per (row, column range), then choose and lay them out
+    const int nr = apsp::pred_sparse_ranges((int32_t)n);
+    const size_t cells = (size_t)nr * (size_t)n;
+    if ((rc = grow(ctx->pred_counts, ctx->pred_counts_bytes, cells * sizeof(int32_t), st, "edge counts")))
+        return rc;
+    HIP_TRY(apsp::launch_edge_count((apsp::DType)dt, W, ldw, (int32_t)n, ctx->pred_counts, st), "edge count launch");
+    std::vector<int32_t> counts(cells);
+    HIP_TRY(hipMemcpyAsync(counts.data(), ctx->pred_counts, cells * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+            "edge count copy");
+    HIP_TRY(hipStreamSynchronize(st), "edge count sync");
+    std::vector<int64_t> offs(cells + nr + 1);   // offsets[r * n + v], then range_start[0..nr]
+    int64_t m = 0;
+    for (int r = 0; r < nr; ++r) {
+        offs[cells + r] = m;
+        for (int64_t v = 0; v < n; ++v) {
+            offs[(size_t)r * n + v] = m;
+            m += counts[(size_t)r * n + v];
+        }
+    }
+    offs[cells + nr] = m;
+    if (method == APSP_PRED_AUTO && (double)m > kPredSparseMaxDensity * (double)n * (double)n) return dense();
+    if ((rc = grow(ctx->pred_offsets, ctx->pred_offsets_bytes, offs.size() * sizeof(int64_t), st, "edge offsets")) ||
+        (rc = grow(ctx->pred_edges, ctx->pred_edges_bytes, (size_t)m * sizeof(uint64_t), st, "edge list")))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->pred_offsets, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                           st),
+            "edge offset upload");
+    const double terms = (double)n * (double)m;
+    rc = timed(ctx, APSP_KERNEL_OTHER, terms, 8.0 * (double)m + 8.0 * n * n, st, [&]() -> apsp_status_t {
+        HIP_TRY(apsp::launch_pred_sparse((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, ctx->pred_offsets,
+                                         ctx->pred_offsets + cells, ctx->pred_edges, st),
+                "sparse predecessor launch");
         return APSP_OK;
     });
+    if (rc) return rc;
+    // the host copy of the offsets must outlive the upload
+    HIP_TRY(hipStreamSynchronize(st), "edge offset sync");
+    return APSP_OK;
 }
+
+apsp_status_t apsp_predecessors(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
+                                const void* W, int64_t ldw, int32_t* P, int64_t ldp, void* stream)
+{
+    return apsp_predecessors_ex(ctx, dt, n, D, ldd, W, ldw, P, ldp, APSP_PRED_AUTO, stream);
+}
+
 
 apsp_status_t apsp_validate(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
                             void* stream, int64_t* h_violations)

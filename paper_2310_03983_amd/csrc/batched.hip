@@ -140,9 +140,13 @@ __global__ __launch_bounds__(dev::kCloseWideThreads) void k_bclose(const BatchPt
     dev::close_block_wide<S>(D + (int64_t)k0 * n + k0, n, min(kB, n - k0), lds);
 }
 
+// Panel tile update of round r (item (graph, r, t, b)): b = 0 the row panel
+// R_KJ <- X* (min,+) R_KJ, b = 1 the column panel C_IK <- C_IK (min,+) X*,
+// one 128 x 128 tile per workgroup.  The tile is read and written by the
+// same workgroup (its reads finish before its epilogue stores), so the
+// in-place update takes only the pre-update panel.
 template <class S>
-__global__ __launch_bounds__(256) void k_btile(const BatchPtrs* __restrict__ bp, const int4* __restrict__ items,
-                                               int phase)
+__global__ __launch_bounds__(256) void k_btile(const BatchPtrs* __restrict__ bp, const int4* __restrict__ items)
 {
     using T = typename S::T;
     using P = typename S::P;
@@ -154,32 +158,23 @@ __global__ __launch_bounds__(256) void k_btile(const BatchPtrs* __restrict__ bp,
     const int64_t ld = n;
     const int k0 = it.y * kB, bk = min(kB, n - k0);
     T* piv = D + (int64_t)k0 * ld + k0;
+    const int o0 = it.z * kB, w = min(kB, n - o0);
     const T* A;
     const T* B;
     T* C;
     int M, N;
-    if (phase == 1) {
-        const int o0 = it.z * kB, w = min(kB, n - o0);
-        if (it.w == 0) {            // row panel R_KJ <- X* (min,+) R_KJ
-            A = piv;
-            C = D + (int64_t)k0 * ld + o0;
-            B = C;
-            M = bk;
-            N = w;
-        } else {                    // column panel C_IK <- C_IK (min,+) X*
-            C = D + (int64_t)o0 * ld + k0;
-            A = C;
-            B = piv;
-            M = w;
-            N = bk;
-        }
-    } else {                        // remainder D_IJ <- min(D_IJ, C_IK (min,+) R_KJ)
-        const int r0 = it.z * kB, c0 = it.w * kB;
-        A = D + (int64_t)r0 * ld + k0;
-        B = D + (int64_t)k0 * ld + c0;
-        C = D + (int64_t)r0 * ld + c0;
-        M = min(kB, n - r0);
-        N = min(kB, n - c0);
+    if (it.w == 0) {            // row panel
+        A = piv;
+        C = D + (int64_t)k0 * ld + o0;
+        B = C;
+        M = bk;
+        N = w;
+    } else {                    // column panel
+        C = D + (int64_t)o0 * ld + k0;
+        A = C;
+        B = piv;
+        M = w;
+        N = bk;
     }
     dev::mp_tile<S, kB, kB, 16, 8, 8, true>(A, ld, B, ld, C, ld, M, N, 0, 0, 0, bk, false, nullptr, As, Bs);
 }
@@ -299,11 +294,13 @@ hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const in
             hipLaunchKernelGGL(k_bclose<dev::SemI32>, dim3(count), dim3(dev::kCloseWideThreads), 0, st, bp, items);
         else
             hipLaunchKernelGGL(k_bclose<dev::SemF32>, dim3(count), dim3(dev::kCloseWideThreads), 0, st, bp, items);
-    } else {
+    } else if (phase == 1) {
         if (dt == I32)
-            hipLaunchKernelGGL(k_btile<dev::SemI32>, dim3(count), dim3(256), 0, st, bp, items, phase);
+            hipLaunchKernelGGL(k_btile<dev::SemI32>, dim3(count), dim3(256), 0, st, bp, items);
         else
-            hipLaunchKernelGGL(k_btile<dev::SemF32>, dim3(count), dim3(256), 0, st, bp, items, phase);
+            hipLaunchKernelGGL(k_btile<dev::SemF32>, dim3(count), dim3(256), 0, st, bp, items);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

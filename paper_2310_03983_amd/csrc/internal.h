@@ -96,10 +96,10 @@ struct BatchPtrs {
 };
 hipError_t launch_batch_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, const int32_t* sizes,
                              hipStream_t st);
-// phase 0: pivot closures; 1: panel tiles; 2: remainder tiles; 3: remainder
-// update of the next pivot tile (r+1, r+1) followed by its closure; 4:
-// remainder on 64 x 64 sub-tiles, sub-tile (si, sj) in bits 8 and 9 of the
-// round (items: int4 {graph, round, a, b}).
+// phase 0: pivot closures; 1: panel tiles; 3: remainder update of the next
+// pivot tile (r+1, r+1) followed by its closure; 4: the other remainder
+// tiles on 64 x 64 sub-tiles, sub-tile (si, sj) in bits 8 and 9 of the round
+// (items: int4 {graph, round, a, b}).  Other phases: hipErrorInvalidValue.
 hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const int4* items, int count,
                               hipStream_t st);
 int batched_round_width();
@@ -111,6 +111,17 @@ const void* batched_kernel(DType dt);
 int batched_max_n();
 
 // ---- last-hop predecessors (pred.hip)
+// Sparse last-hop predecessors: column ranges of 1024, edges packed as
+// v | (j - range start) << 16 | cost bits << 32, ordered by v within a range.
+// launch_edge_count fills counts[r * n + v] (edges of row v in range r);
+// launch_pred_sparse writes the edges at offsets[r * n + v] and then P, using
+// range_start[0..ranges] (edge index of each range's first edge).  n <= 65535.
+int pred_sparse_ranges(int32_t n);
+hipError_t launch_edge_count(DType dt, const void* W, int64_t ldw, int32_t n, int32_t* counts, hipStream_t st);
+hipError_t launch_pred_sparse(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
+                              int64_t ldp, int32_t n, const int64_t* offsets, const int64_t* range_start,
+                              uint64_t* edges, hipStream_t st);
+
 hipError_t launch_predecessors(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
                                int64_t ldp, int32_t n, hipStream_t st);
 

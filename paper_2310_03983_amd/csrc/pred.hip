@@ -85,7 +85,182 @@ __global__ __launch_bounds__(256) void k_predecessors(const typename S::T* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sparse form.  A term D[i][v] (+) W[v][j] can fall below INF only when
+// W[v][j] < INF, and v == j is excluded, so P[i][j] is the same argmin taken
+// over the in-edges of j alone: n * m candidate terms instead of n^3 for m
+// edges.  The columns are cut into ranges of kRange; the edges of each range
+// are stored contiguously, ordered by source v, one 64-bit word each:
+//   bits 0..15 v, bits 16..31 j - range start, bits 32..63 the cost's bits.
+// k_pred_sparse: a workgroup owns kRows rows of D and one column range and
+// keeps one 64-bit key per (row, column) in LDS:
+//   key = (bits of D[i][v] (+) W[v][j]) << 32 | v,
+// folded with an LDS 64-bit atomic min.  Non-negative int32 values and
+// non-negative binary32 values both order like their bit patterns, so the
+// minimum key is the minimum value, ties broken by the smallest v -- the
+// same answer as the dense kernel, whatever order the atomics land in.
+// ---------------------------------------------------------------------------
+constexpr int kRange = 1024;          // columns per range (j - start fits 16 bits)
+constexpr int kRows = 8;              // rows of D per workgroup (LDS keys: 64 KB)
+
+template <class S>
+__device__ __forceinline__ bool finite_cost(typename S::T w) { return w < S::inf(); }
+
+// Order-preserving key bits of a non-negative value (fp32: + 0.0f turns a
+// -0 sum into +0, which the dense kernel's compare also treats as 0).
+__device__ __forceinline__ uint32_t key_bits(uint32_t s) { return s; }
+__device__ __forceinline__ uint32_t key_bits(float s) { return __builtin_bit_cast(uint32_t, s + 0.0f); }
+
+// counts[r * n + v] = edges of row v (v -> j, j != v, W finite) with j in range r
+template <class S>
+__global__ __launch_bounds__(256) void k_edge_count(const typename S::T* __restrict__ W, int64_t ldw, int n,
+                                                    int nranges, int32_t* __restrict__ counts)
+{
+    __shared__ int32_t cnt[64];
+    const int v = blockIdx.x;
+    for (int r = threadIdx.x; r < nranges; r += 256) cnt[r] = 0;
+    __syncthreads();
+    const typename S::T* row = W + (int64_t)v * ldw;
+    for (int j = threadIdx.x; j < n; j += 256)
+        if (j != v && finite_cost<S>(row[j])) atomicAdd(&cnt[j / kRange], 1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < nranges; r += 256) counts[(int64_t)r * n + v] = cnt[r];
+}
+
+// Writes row v's edges of every range at offsets[r * n + v], in increasing j.
+template <class S>
+__global__ __launch_bounds__(256) void k_edge_fill(const typename S::T* __restrict__ W, int64_t ldw, int n,
+                                                   int nranges, const int64_t* __restrict__ offsets,
+                                                   uint64_t* __restrict__ edges)
+{
+    using T = typename S::T;
+    __shared__ int32_t wave_tot[4];
+    const int v = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const T* row = W + (int64_t)v * ldw;
+    for (int r = 0; r < nranges; ++r) {
+        int64_t pos = offsets[(int64_t)r * n + v];
+        const int j1 = min(n, (r + 1) * kRange);
+        for (int c0 = r * kRange; c0 < j1; c0 += 256) {
+            const int j = c0 + threadIdx.x;
+            T w{};
+            bool f = false;
+            if (j < j1) {
+                w = row[j];
+                f = j != v && finite_cost<S>(w);
+            }
+            const uint64_t mask = __ballot(f);
+            const int before = __popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == 0) wave_tot[wave] = __popcll(mask);
+            __syncthreads();
+            int base = 0;
+            for (int q = 0; q < wave; ++q) base += wave_tot[q];
+            if (f) {
+                const uint32_t lo = (uint32_t)v | ((uint32_t)(j - r * kRange) << 16);
+                edges[pos + base + before] = ((uint64_t)__builtin_bit_cast(uint32_t, w) << 32) | lo;
+            }
+            pos += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+            __syncthreads();
+        }
+    }
+}
+
+constexpr int kSparseThreads = 512;   // two workgroups (64 KB of keys each) fill a CU's waves
+
+template <class S>
+__global__ __launch_bounds__(kSparseThreads) void k_pred_sparse(const typename S::T* __restrict__ D, int64_t ldd,
+                                                                int n, const int64_t* __restrict__ range_start,
+                                                                const uint64_t* __restrict__ edges,
+                                                                int32_t* __restrict__ P, int64_t ldp)
+{
+    using T = typename S::T;
+    __shared__ unsigned long long best[kRows * kRange];
+    const int i0 = blockIdx.x * kRows, r = blockIdx.y;
+    const int rows = min(kRows, n - i0);
+    for (int e = threadIdx.x; e < kRows * kRange; e += kSparseThreads) best[e] = ~0ull;
+    __syncthreads();
+    const T* Drows = D + (int64_t)i0 * ldd;
+    const int64_t e1 = range_start[r + 1];
+    // kEdges edges per lane per step: all their D loads are issued before
+    // the first atomic, so the loads of one step overlap
+    constexpr int kEdges = 4;
+    for (int64_t e = range_start[r] + threadIdx.x; e < e1; e += kEdges * kSparseThreads) {
+        int v[kEdges], jr[kEdges];
+        T w[kEdges], d[kEdges][kRows];
+        bool ok[kEdges];
+#pragma unroll
+        for (int q = 0; q < kEdges; ++q) {
+            const int64_t eq = e + (int64_t)q * kSparseThreads;
+            ok[q] = eq < e1;
+            const uint64_t ed = edges[ok[q] ? eq : e];
+            v[q] = (int)(ed & 0xffff);
+            jr[q] = (int)((ed >> 16) & 0xffff);
+            w[q] = __builtin_bit_cast(T, (uint32_t)(ed >> 32));
+        }
+#pragma unroll
+        for (int q = 0; q < kEdges; ++q)
+#pragma unroll
+            for (int ii = 0; ii < kRows; ++ii) d[q][ii] = Drows[(int64_t)min(ii, rows - 1) * ldd + v[q]];
+#pragma unroll
+        for (int ii = 0; ii < kRows; ++ii) {
+            if (ii >= rows) break;
+#pragma unroll
+            for (int q = 0; q < kEdges; ++q) {
+                const T sv = d[q][ii] + w[q];   // int32: <= 2^31, no wrap
+                if (ok[q])
+                    atomicMin(&best[ii * kRange + jr[q]],
+                              ((unsigned long long)key_bits(sv) << 32) | (unsigned long long)v[q]);
+            }
+        }
+    }
+    __syncthreads();
+    const int jbase = r * kRange, width = min(kRange, n - jbase);
+    for (int e = threadIdx.x; e < rows * kRange; e += kSparseThreads) {
+        const int ii = e / kRange, jr = e - ii * kRange;
+        if (jr >= width) continue;
+        const int i = i0 + ii, j = jbase + jr;
+        const unsigned long long key = best[e];
+        const T s = __builtin_bit_cast(T, (uint32_t)(key >> 32));
+        const bool none = key == ~0ull || i == j || !(s < S::inf());
+        P[(int64_t)i * ldp + j] = none ? -1 : (int32_t)(key & 0xffffffffu);
+    }
+}
+
 }  // namespace
+
+int pred_sparse_ranges(int32_t n) { return (n + kRange - 1) / kRange; }
+
+hipError_t launch_edge_count(DType dt, const void* W, int64_t ldw, int32_t n, int32_t* counts, hipStream_t st)
+{
+    const int nr = pred_sparse_ranges(n);
+    if (dt == I32)
+        hipLaunchKernelGGL(k_edge_count<dev::SemI32>, dim3(n), dim3(256), 0, st, (const uint32_t*)W, ldw, n, nr,
+                           counts);
+    else
+        hipLaunchKernelGGL(k_edge_count<dev::SemF32>, dim3(n), dim3(256), 0, st, (const float*)W, ldw, n, nr,
+                           counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_pred_sparse(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
+                              int64_t ldp, int32_t n, const int64_t* offsets, const int64_t* range_start,
+                              uint64_t* edges, hipStream_t st)
+{
+    const int nr = pred_sparse_ranges(n);
+    const dim3 grid((unsigned)((n + kRows - 1) / kRows), (unsigned)nr);
+    if (dt == I32) {
+        hipLaunchKernelGGL(k_edge_fill<dev::SemI32>, dim3(n), dim3(256), 0, st, (const uint32_t*)W, ldw, n, nr,
+                           offsets, edges);
+        hipLaunchKernelGGL(k_pred_sparse<dev::SemI32>, grid, dim3(kSparseThreads), 0, st, (const uint32_t*)D, ldd,
+                           n, range_start, edges, P, ldp);
+    } else {
+        hipLaunchKernelGGL(k_edge_fill<dev::SemF32>, dim3(n), dim3(256), 0, st, (const float*)W, ldw, n, nr,
+                           offsets, edges);
+        hipLaunchKernelGGL(k_pred_sparse<dev::SemF32>, grid, dim3(kSparseThreads), 0, st, (const float*)D, ldd,
+                           n, range_start, edges, P, ldp);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_predecessors(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
                                int64_t ldp, int32_t n, hipStream_t st)

@@ -181,3 +181,18 @@ def test_packed16_option_is_checked_before_any_device_call(native):
     assert L.apsp_batched(None, 0, 1, fake, fake, fake, n, ctypes.byref(o), None) == native.APSP_E_UNSUPPORTED
     runs, redone = ctypes.c_int64(), ctypes.c_int64()
     assert L.apsp_packed16_counts(None, ctypes.byref(runs), ctypes.byref(redone)) == native.APSP_E_ARG
+
+
+def test_predecessors_ex_argument_errors(native):
+    L = native.lib()
+    D, W, P = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    f = L.apsp_predecessors_ex
+    assert f(None, 0, 4, D, 4, W, 4, P, 4, 3, None) == native.APSP_E_ARG
+    assert "method" in native.last_error()
+    assert f(None, 0, 4, D, 4, W, 4, P, 4, -1, None) == native.APSP_E_ARG
+    big = 65536
+    far = [ctypes.c_void_p(k << 36) for k in (1, 2, 3)]
+    assert f(None, 0, big, far[0], big, far[1], big, far[2], big, native.PRED["sparse"], None) == \
+        native.APSP_E_UNSUPPORTED
+    assert f(None, 0, 4, D, 4, W, 4, P, 4, native.PRED["sparse"], None) == native.APSP_E_ARG
+    assert "context" in native.last_error()

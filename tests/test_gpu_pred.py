@@ -91,3 +91,52 @@ def test_predecessors_f32_valid(native, dev):
             path = native.reconstruct_path(Ph[i], i, j)
             w = sum(float(W[a, b]) for a, b in zip(path, path[1:]))
             assert abs(w - ref[i, j]) <= 1e-5 * ref[i, j]
+
+
+def run_form(native, D, W, dev, method):
+    P = native.apsp_predecessors(torch.from_numpy(D).to(dev), torch.from_numpy(W).to(dev), method=method)
+    torch.cuda.synchronize()
+    return P.cpu().numpy()
+
+
+@pytest.mark.parametrize("closure", [True, False])
+def test_predecessor_forms_agree_i32(native, dev, closure):
+    """Dense, sparse and automatic forms give the oracle's P, for D the
+    closure of W and for an arbitrary D (the definition covers any D)."""
+    rng = np.random.default_rng(1100 + closure)
+    for n, p in ((1, 0.5), (2, 1.0), (3, 0.0), (63, 0.05), (64, 0.3), (65, 1.0), (300, 0.01),
+                 (1023, 0.004), (1024, 0.02), (1025, 0.002), (1100, 0.0)):
+        W = rand_graph(rng, n, p, 1, 8)                         # small costs: many ties
+        if closure:
+            D = oracle.fw_i32(W)
+        else:
+            D = rng.integers(0, 40, (n, n)).astype(np.int32)
+            D[rng.random((n, n)) < 0.2] = INF
+        ref = oracle.predecessors_i32(D, W)
+        for method in ("dense", "sparse", "auto"):
+            np.testing.assert_array_equal(run_form(native, D, W, dev, method), ref, err_msg=f"n={n} p={p} {method}")
+
+
+def test_predecessor_forms_agree_f32(native, dev):
+    rng = np.random.default_rng(1200)
+    for n, p in ((5, 0.5), (130, 0.05), (1030, 0.01)):
+        W = np.where(rng.random((n, n)) < p, rng.uniform(0.1, 10.0, (n, n)), np.inf).astype(np.float32)
+        np.fill_diagonal(W, 0.0)
+        Wd = torch.from_numpy(W).to(dev)
+        D = Wd.clone()
+        native.apsp_solve(D)
+        Dh = D.cpu().numpy()
+        dense = run_form(native, Dh, W, dev, "dense")
+        np.testing.assert_array_equal(run_form(native, Dh, W, dev, "sparse"), dense, err_msg=f"n={n}")
+
+
+def test_predecessor_forms_agree_n4096(native, dev):
+    wl = gg.SINGLE["n4096_p0.05_i32"]
+    W = wl.make()
+    Wd = torch.from_numpy(W).to(dev)
+    D = Wd.clone()
+    native.apsp_solve(D)
+    Ps = native.apsp_predecessors(D, Wd, method="sparse")
+    Pd = native.apsp_predecessors(D, Wd, method="dense")
+    torch.cuda.synchronize()
+    assert torch.equal(Ps, Pd)
