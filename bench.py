@@ -131,7 +131,7 @@ def bench_small(torch, apsp, gg, dev):
     for method in ("dense", "sparse"):
         t = time_predecessors(torch, apsp, D4k, W4k, method, 10)
         out[f"n4096_predecessors_{method}_i32"] = {"ms_per_call": t * 1e3, "edges": m,
-                                                   "candidate_terms_per_s": 4096 * (4096 if method == "dense" else m) / t}
+                                                   "candidate_terms_per_s": 4096 * (4096 * 4096 if method == "dense" else m) / t}
     return out
 
 
