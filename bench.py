@@ -125,6 +125,13 @@ def bench_small(torch, apsp, gg, dev):
     for label, fn in (("n4096_fw_i32", apsp.apsp_fw), ("n4096_rkleene_i32", apsp.apsp_rkleene)):
         t = per_solve(fn, W4k, 20)
         out[label] = {"ms_per_solve": t * 1e3, "updates_per_s": 4096 ** 3 / t}
+    # a graph sparse enough (mean degree 0.8) that many reduction slices are
+    # all INF: blocked FW with and without APSP_FLAG_SKIP_INF
+    Wsp = torch.from_numpy(gg.graph_i32(8192, 1e-4, 1, 1000, gg.graph_seed(9, 100))).to(dev)
+    for label, kw in (("n8192_p0.0001_fw_i32", {}), ("n8192_p0.0001_fw_i32_skip_inf", {"skip_inf": True})):
+        t = per_solve(lambda d: apsp.apsp_fw(d, **kw), Wsp, 5)
+        out[label] = {"ms_per_solve": t * 1e3, "updates_per_s": 8192 ** 3 / t}
+    del Wsp
     D4k = W4k.clone()
     apsp.apsp_fw(D4k)
     m = int(torch.count_nonzero(W4k < (1 << 30)).item()) - 4096

@@ -86,6 +86,12 @@ typedef int32_t apsp_dtype_t;
 #define APSP_FLAG_BATCH_PERSISTENT 16 /* apsp_batched: one persistent kernel, one workgroup per graph */
 #define APSP_FLAG_PACKED16         32 /* int32 apsp_fw / apsp_rkleene / apsp_square / apsp_solve:
                                          min-plus products in capped 16-bit arithmetic (see below) */
+#define APSP_FLAG_SKIP_INF         64 /* minplus_gemm / apsp_fw / apsp_rkleene / apsp_square / apsp_solve:
+                                         a product skips every reduction slice (16 or 32 steps of one
+                                         tile) whose A block or B block is all INF -- exact, since
+                                         C <= INF; pays off on very sparse graphs, costs a few
+                                         instructions per slice otherwise.  apsp_closure and
+                                         apsp_batched ignore it. */
 
 typedef struct apsp_opts {
     int32_t algo;      /* APSP_ALGO_*; only apsp_solve and apsp_batched read it */

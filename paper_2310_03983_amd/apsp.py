@@ -25,6 +25,7 @@ CLOSURE = {"auto": 0, "kloop": 1, "square": 2}
 TILE = {"auto": 0, 128: 1, 64: 2}
 FLAG_NO_SPLITK, FLAG_BATCH_NO_GRAPH, FLAG_BATCH_PER_GRAPH, FLAG_NO_LOOKAHEAD, FLAG_BATCH_PERSISTENT = 1, 2, 4, 8, 16
 FLAG_PACKED16 = 32
+FLAG_SKIP_INF = 64
 CAP16 = 0x39FF    # 14847: cap of the APSP_FLAG_PACKED16 products
 
 # every symbol include/apsp.h declares
@@ -67,7 +68,7 @@ class KernelStats(ctypes.Structure):
 
 def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True,
               batch_graph=True, batch_per_graph=False, lookahead=True, batch_persistent=False,
-              packed16=False) -> Opts:
+              packed16=False, skip_inf=False) -> Opts:
     o = Opts()
     o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
     o.block = int(block)
@@ -76,7 +77,8 @@ def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, spli
     o.cutover = int(cutover)
     o.flags = (0 if splitk else FLAG_NO_SPLITK) | (0 if batch_graph else FLAG_BATCH_NO_GRAPH) | \
         (FLAG_BATCH_PER_GRAPH if batch_per_graph else 0) | (0 if lookahead else FLAG_NO_LOOKAHEAD) | \
-        (FLAG_BATCH_PERSISTENT if batch_persistent else 0) | (FLAG_PACKED16 if packed16 else 0)
+        (FLAG_BATCH_PERSISTENT if batch_persistent else 0) | (FLAG_PACKED16 if packed16 else 0) | \
+        (FLAG_SKIP_INF if skip_inf else 0)
     return o
 
 

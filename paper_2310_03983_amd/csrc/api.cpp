@@ -208,6 +208,7 @@ struct Plan {
     bool splitk;
     bool lookahead; // FW: overlap the next pivot and panels with the remainder
     bool p16;       // int32: min-plus products in capped 16-bit arithmetic
+    bool skip;      // products skip reduction slices with an all-INF operand
 };
 
 Plan resolve(const apsp_opts_t* o)
@@ -220,6 +221,7 @@ Plan resolve(const apsp_opts_t* o)
     p.splitk = !(o->flags & APSP_FLAG_NO_SPLITK);
     p.lookahead = !(o->flags & APSP_FLAG_NO_LOOKAHEAD);
     p.p16 = (o->flags & APSP_FLAG_PACKED16) != 0;
+    p.skip = (o->flags & APSP_FLAG_SKIP_INF) != 0;
     return p;
 }
 
@@ -268,7 +270,7 @@ apsp_status_t run_group(apsp_ctx_t* ctx, apsp_dtype_t dt, apsp::GemmGroup& g, co
     group_work(g, tile, terms, bytes);
     const int kind = tile == apsp::TILE_64 ? APSP_KERNEL_MINPLUS_64 : APSP_KERNEL_MINPLUS_128;
     return timed(ctx, kind, terms, bytes, st, [&]() -> apsp_status_t {
-        HIP_TRY(apsp::launch_minplus(gdt, tile, g, st), "min-plus launch");
+        HIP_TRY(apsp::launch_minplus(gdt, tile, g, pl.skip, st), "min-plus launch");
         return APSP_OK;
     });
 }
@@ -476,7 +478,7 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
         const double terms = (double)n * n * n;
         rc = timed(ctx, tile == apsp::TILE_64 ? APSP_KERNEL_MINPLUS_64 : APSP_KERNEL_MINPLUS_128, terms,
                    16.0 * n * n, st, [&]() -> apsp_status_t {
-                       HIP_TRY(apsp::launch_square_pass(gemm_dtype(dt, pl), tile, D, n, ld, flag, st),
+                       HIP_TRY(apsp::launch_square_pass(gemm_dtype(dt, pl), tile, D, n, ld, flag, pl.skip, st),
                                "squaring pass");
                        return APSP_OK;
                    });

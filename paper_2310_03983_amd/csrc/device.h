@@ -170,7 +170,13 @@ struct Cfg {
 // As/Bs: LDS staging of 2 x KT/KPACK x (MT+2) and 2 x KT/KPACK x (NT+2)
 // packed words.
 // ---------------------------------------------------------------------------
-template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC>
+// SKIP: a slice whose staged A values, or whose staged B values, are all INF
+// is not folded -- each of its terms is >= INF and the accumulator starts at
+// C <= INF, so it could change nothing.  Lanes that stage a finite value
+// write the slice's number into an LDS word per buffer and operand; after
+// the barrier every lane reads the same words, so the choice is uniform, and
+// a word written for slice s is never read for another slice (no reset).
+template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC, bool SKIP = false>
 __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int64_t lda,
                                         const typename S::T* __restrict__ B, int64_t ldb,
                                         typename S::T* C, int64_t ldc, int M, int N,
@@ -321,38 +327,72 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
         }
     };
 
+    __shared__ int live[2][2];   // [buffer][A, B]: last slice with a finite staged value (SKIP)
+    auto mark = [&](int buf, int sidx) {
+        if constexpr (SKIP) {
+            bool fa = false, fb = false;
+#pragma unroll
+            for (int q = 0; q < C_::A_PER; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) fa |= ra[q][e] < S::inf();
+#pragma unroll
+            for (int q = 0; q < C_::B_PER; ++q)
+#pragma unroll
+                for (int h = 0; h < KPACK; ++h)
+#pragma unroll
+                    for (int e = 0; e < BV; ++e) fb |= rb[q][h][e] < S::inf();
+            // one lane per wave writes (same-address LDS writes serialise)
+            const bool wa = __any(fa), wb = __any(fb);
+            if ((tid & (warpSize - 1)) == 0) {
+                if (wa) live[buf][0] = sidx;
+                if (wb) live[buf][1] = sidx;
+            }
+        }
+    };
+
     const int nslices = (kend > kbeg) ? (kend - kbeg + KT - 1) / KT : 0;
     if (nslices > 0) {
         load_slice(kbeg);
         store_slice(0);
+        mark(0, 0);
         __syncthreads();
         for (int s = 0; s < nslices; ++s) {
             const int cur = s & 1;
             if (s + 1 < nslices) load_slice(kbeg + (s + 1) * KT);
             // two pair-steps per iteration: enough independent work to hide
             // LDS latency without hoisting every slice read into registers
+            auto fold_slice = [&]() {
 #pragma unroll 2
-            for (int p = 0; p < KP; ++p) {
-                P a[TM], b[TN];
+                for (int p = 0; p < KP; ++p) {
+                    P a[TM], b[TN];
 #pragma unroll
-                for (int g = 0; g < C_::GM; ++g) {
-                    const auto v = *reinterpret_cast<const Pair2<P>*>(&As[cur][p][g * C_::SM + ty * 2]);
-                    a[2 * g] = v.x;
-                    a[2 * g + 1] = v.y;
+                    for (int g = 0; g < C_::GM; ++g) {
+                        const auto v = *reinterpret_cast<const Pair2<P>*>(&As[cur][p][g * C_::SM + ty * 2]);
+                        a[2 * g] = v.x;
+                        a[2 * g + 1] = v.y;
+                    }
+#pragma unroll
+                    for (int g = 0; g < C_::GN; ++g) {
+                        const auto v = *reinterpret_cast<const Pair2<P>*>(&Bs[cur][p][g * C_::SN + tx * 2]);
+                        b[2 * g] = v.x;
+                        b[2 * g + 1] = v.y;
+                    }
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
                 }
-#pragma unroll
-                for (int g = 0; g < C_::GN; ++g) {
-                    const auto v = *reinterpret_cast<const Pair2<P>*>(&Bs[cur][p][g * C_::SN + tx * 2]);
-                    b[2 * g] = v.x;
-                    b[2 * g + 1] = v.y;
-                }
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = S::fold(acc[i][j], a[i], b[j]);
+            };
+            if constexpr (SKIP) {
+                if (live[cur][0] == s && live[cur][1] == s) fold_slice();
+            } else {
+                fold_slice();
             }
-            if (s + 1 < nslices) store_slice(cur ^ 1);
+            if (s + 1 < nslices) {
+                store_slice(cur ^ 1);
+                mark(cur ^ 1, s + 1);
+            }
             __syncthreads();
         }
     }

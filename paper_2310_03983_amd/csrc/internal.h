@@ -53,7 +53,8 @@ TileShape tile_shape(int tile, DType dt = I32);
 // split_target: desired number of workgroups (0 disables split-K).
 void finalize_group(GemmGroup& g, int tile, int split_target, DType dt = I32);
 
-hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, hipStream_t s);
+// skip: reduction slices whose staged A or B values are all INF are not folded.
+hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, bool skip, hipStream_t s);
 
 // Closure of an s x s diagonal block (s <= 128) held at D (leading dim ld).
 // kind: 1 = Eq. 1 k-loop, 2 = squaring to a fixpoint.
@@ -75,7 +76,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s
 // One min-plus squaring pass D <- min(D, D (min,+) D) with change detection:
 // *d_changed is set to 1 when any entry decreased.
 hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld,
-                              uint32_t* d_changed, hipStream_t st);
+                              uint32_t* d_changed, bool skip, hipStream_t st);
 
 // Ragged batch: graph g is the n x n row-major matrix at data + offsets[g]
 // (elements), n = sizes[g].  Workgroups take graphs in the order order[0..count).

@@ -39,7 +39,7 @@ using dev::SemF32;
 using dev::SemI32;
 using dev::SemP16;
 
-template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC>
+template <class S, int MT, int NT, int KT, int TM, int TN, bool VEC, bool SKIP>
 __global__ __launch_bounds__((MT / TM) * (NT / TN))
 void k_minplus(const GemmGroup G, uint32_t* __restrict__ changed)
 {
@@ -77,13 +77,13 @@ void k_minplus(const GemmGroup G, uint32_t* __restrict__ changed)
     const int kbeg = split * Pb.kchunk;
     const int kend = min(Pb.K, kbeg + Pb.kchunk);
 
-    dev::mp_tile<S, MT, NT, KT, TM, TN, VEC>(static_cast<const T*>(Pb.A), Pb.lda, static_cast<const T*>(Pb.B),
+    dev::mp_tile<S, MT, NT, KT, TM, TN, VEC, SKIP>(static_cast<const T*>(Pb.A), Pb.lda, static_cast<const T*>(Pb.B),
                                              Pb.ldb, static_cast<T*>(Pb.C), Pb.ldc, Pb.M, Pb.N, tm * MT, tn * NT,
                                              kbeg, kend, Pb.ksplit > 1, changed, As, Bs);
 }
 
 template <class S, int MT, int NT, int KT, int TM, int TN>
-hipError_t launch_cfg(const GemmGroup& g, uint32_t* changed, hipStream_t st)
+hipError_t launch_cfg(const GemmGroup& g, uint32_t* changed, bool skip, hipStream_t st)
 {
     using C_ = Cfg<S, MT, NT, KT, TM, TN>;
     bool vec = true;
@@ -94,10 +94,17 @@ hipError_t launch_cfg(const GemmGroup& g, uint32_t* changed, hipStream_t st)
         if (!al(p.A) || !al(p.B) || !al(p.C)) vec = false;
     }
     dim3 grid(g.total_wgs), block(C_::NTHR);
-    if (vec)
-        hipLaunchKernelGGL((k_minplus<S, MT, NT, KT, TM, TN, true>), grid, block, 0, st, g, changed);
-    else
-        hipLaunchKernelGGL((k_minplus<S, MT, NT, KT, TM, TN, false>), grid, block, 0, st, g, changed);
+    if (skip) {
+        if (vec)
+            hipLaunchKernelGGL((k_minplus<S, MT, NT, KT, TM, TN, true, true>), grid, block, 0, st, g, changed);
+        else
+            hipLaunchKernelGGL((k_minplus<S, MT, NT, KT, TM, TN, false, true>), grid, block, 0, st, g, changed);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_minplus<S, MT, NT, KT, TM, TN, true, false>), grid, block, 0, st, g, changed);
+        else
+            hipLaunchKernelGGL((k_minplus<S, MT, NT, KT, TM, TN, false, false>), grid, block, 0, st, g, changed);
+    }
     return hipGetLastError();
 }
 
@@ -106,18 +113,18 @@ hipError_t launch_cfg(const GemmGroup& g, uint32_t* changed, hipStream_t st)
 // staging registers then stay few enough for three waves per SIMD, and
 // takes 64 for 64-tiles.
 template <class S>
-hipError_t launch_sem(int tile, const GemmGroup& g, uint32_t* changed, hipStream_t st)
+hipError_t launch_sem(int tile, const GemmGroup& g, uint32_t* changed, bool skip, hipStream_t st)
 {
     constexpr int X = S::KPACK / 2;
-    if (tile == TILE_64) return launch_cfg<S, 64, 64, 32 * X, 4, 4>(g, changed, st);
-    return launch_cfg<S, 128, 128, 16, 8, 8>(g, changed, st);
+    if (tile == TILE_64) return launch_cfg<S, 64, 64, 32 * X, 4, 4>(g, changed, skip, st);
+    return launch_cfg<S, 128, 128, 16, 8, 8>(g, changed, skip, st);
 }
 
-hipError_t launch_dtype(DType dt, int tile, const GemmGroup& g, uint32_t* changed, hipStream_t st)
+hipError_t launch_dtype(DType dt, int tile, const GemmGroup& g, uint32_t* changed, bool skip, hipStream_t st)
 {
-    if (dt == I32) return launch_sem<SemI32>(tile, g, changed, st);
-    if (dt == I32P16) return launch_sem<SemP16>(tile, g, changed, st);
-    return launch_sem<SemF32>(tile, g, changed, st);
+    if (dt == I32) return launch_sem<SemI32>(tile, g, changed, skip, st);
+    if (dt == I32P16) return launch_sem<SemP16>(tile, g, changed, skip, st);
+    return launch_sem<SemF32>(tile, g, changed, skip, st);
 }
 
 }  // namespace
@@ -165,14 +172,14 @@ void finalize_group(GemmGroup& g, int tile, int split_target, DType dt)
     g.total_wgs = wg;
 }
 
-hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, hipStream_t st)
+hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, bool skip, hipStream_t st)
 {
     if (g.total_wgs <= 0) return hipSuccess;
-    return launch_dtype(dt, tile, g, nullptr, st);
+    return launch_dtype(dt, tile, g, nullptr, skip, st);
 }
 
 hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld,
-                              uint32_t* d_changed, hipStream_t st)
+                              uint32_t* d_changed, bool skip, hipStream_t st)
 {
     GemmGroup g{};
     g.count = 1;
@@ -182,7 +189,7 @@ hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld
     p.M = p.N = p.K = (int32_t)n;
     finalize_group(g, tile, 0, dt);
     if (g.total_wgs <= 0) return hipSuccess;
-    return launch_dtype(dt, tile, g, d_changed, st);
+    return launch_dtype(dt, tile, g, d_changed, skip, st);
 }
 
 }  // namespace apsp
