@@ -252,7 +252,8 @@ apsp_status_t apsp_predecessors_ex(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t 
  * beside every other remainder tile -- after one launch of all round-0 pivot
  * closures; at most 3 * ceil(max n / 128) launches, captured once per batch
  * shape in a HIP graph and replayed (the buffers of each call are written to
- * a small device record first, so any buffers work).
+ * a small device record first, so any buffers work); when every graph has
+ * n <= 128 the schedule is the one closure launch, issued directly.
  * APSP_FLAG_BATCH_PERSISTENT: one persistent kernel whose workgroups take
  * whole graphs, largest first, from an atomic queue (also graph-captured).
  * APSP_FLAG_BATCH_NO_GRAPH launches directly; APSP_FLAG_BATCH_PER_GRAPH

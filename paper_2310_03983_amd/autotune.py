@@ -3,6 +3,7 @@
     python -m paper_2310_03983_amd.autotune sweep --db timings.json [--first G0 --last G1]
     python -m paper_2310_03983_amd.autotune train --db timings.json --model model.json
     python -m paper_2310_03983_amd.autotune evaluate --db timings.json --model model.json
+    python -m paper_2310_03983_amd.autotune batch --db batch_timings.json
 
 `sweep` times every candidate plan of the library (apsp_candidate) on every
 graph of the 200-graph sweep workload (n log-uniform in [64, 32768], p
@@ -18,6 +19,11 @@ candidates, standardised with one global mean/deviation (so the per-row
 argmin is unchanged).  `evaluate` reports, on held-out graphs, the regret
 t(pick)/t(best) - 1 of the model's pick against exhaustive tuning, next to
 the best single static candidate and the library's size rule.
+
+`batch` times every schedule of apsp_batched (lock-step graph replay,
+lock-step direct launches, persistent kernel, one launch per graph) on the
+512-graph ragged batch and on each size class of it, checks that they agree,
+and writes the winner per class.
 """
 from __future__ import annotations
 
@@ -172,6 +178,60 @@ def sweep(db_path, first=0, last=199, progress=print):
 
 
 # ---------------------------------------------------------------------------
+# batched schedules, per size class
+# ---------------------------------------------------------------------------
+
+BATCH_SCHEDULES = {
+    "lockstep": {},
+    "lockstep_direct": {"batch_graph": False},
+    "persistent": {"batch_persistent": True},
+    "per_graph": {"batch_persistent": True, "batch_per_graph": True},
+}
+SIZE_CLASSES = [(32, 64), (64, 128), (128, 256), (256, 513)]
+
+
+def sweep_batch(reps=10, progress=print):
+    """Times every batched schedule of apsp_batched on the 512-graph ragged
+    batch and on its size classes (graphs with n in [lo, hi)), each class
+    packed as a batch of its own; checks that all schedules give the same
+    distances; returns {class: {schedule: ms, "best": name}}."""
+    import torch
+    from . import apsp
+    dev = torch.device("cuda:0")
+    batch = gg.batch_ragged()
+    mats = [gg.batch_graph_i32(b) for b in batch]
+    classes = [("all", 0, 1 << 30)] + [(f"n{lo}-{hi - 1}", lo, hi) for lo, hi in SIZE_CLASSES]
+    out = {}
+    for name, lo, hi in classes:
+        sel = [m for m in mats if lo <= m.shape[0] < hi]
+        flat, off, sz = gg.pack_batch(sel)
+        flat_d = torch.from_numpy(flat).to(dev)
+        off_d, sz_d = torch.from_numpy(off).to(dev), torch.from_numpy(sz).to(dev)
+        hs = sz.tolist()
+        rec, ref = {"graphs": len(sel)}, None
+        for sched, kw in BATCH_SCHEDULES.items():
+            r = max(2, reps // 5) if sched == "per_graph" else reps
+            copies = [flat_d.clone() for _ in range(r + 1)]
+            apsp.apsp_batched(copies[0], off_d, sz_d, hs, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in copies[1:]:
+                apsp.apsp_batched(c, off_d, sz_d, hs, **kw)
+            torch.cuda.synchronize()
+            rec[sched] = (time.perf_counter() - t0) / r * 1e3
+            if ref is None:
+                ref = copies[-1]
+            elif not torch.equal(ref, copies[-1]):
+                raise RuntimeError(f"schedule {sched} disagrees on class {name}")
+            del copies
+        rec["best"] = min(BATCH_SCHEDULES, key=lambda k: rec[k])
+        out[name] = rec
+        progress(f"[autotune] batch class {name}: {len(sel)} graphs, best {rec['best']} "
+                 + " ".join(f"{k}={rec[k]:.3f}ms" for k in BATCH_SCHEDULES))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # cost model
 # ---------------------------------------------------------------------------
 
@@ -264,7 +324,7 @@ def evaluate(db, model, test_ids, train_ids):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["sweep", "train", "evaluate"])
+    ap.add_argument("cmd", choices=["sweep", "train", "evaluate", "batch"])
     ap.add_argument("--db", required=True)
     ap.add_argument("--model")
     ap.add_argument("--first", type=int, default=0)
@@ -274,6 +334,13 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
         sweep(a.db, a.first, a.last, progress=lambda m: print(m, flush=True))
+        return 0
+    if a.cmd == "batch":
+        import torch
+        res = sweep_batch(progress=lambda m: print(m, flush=True))
+        with open(a.db, "w") as f:
+            json.dump({"device": torch.cuda.get_device_name(0), "schedules": BATCH_SCHEDULES, "classes": res}, f,
+                      indent=1)
         return 0
     db = load_db(a.db)
     train_ids = list(range(a.train_count))
