@@ -225,55 +225,77 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
     constexpr int BV = C_::BV;
     T rb[C_::B_PER][KPACK][BV];
 
-    auto load_slice = [&](int k0) {
+    // Per-lane parts of the staging addresses, formed once per tile: each
+    // slice then adds only a uniform offset (k0 for A, (k0 + h) * ldb for
+    // B), so no 64-bit multiply runs inside the slice loop.
+    int64_t a_off[C_::A_PER];   // (m0 + row) * lda + 4 * c4
+    int64_t b_off[C_::B_PER];   // KPACK * p * ldb + gc
 #pragma unroll
-        for (int q = 0; q < C_::A_PER; ++q) {
-            const int L = tid + q * C_::NTHR;
-            const int row = L / (KT / 4);
-            const int c4 = L % (KT / 4);
-            const int gr = m0 + row;
-            const int gk = k0 + c4 * 4;
-            if (VEC && gr < M && gk + 3 < kend) {
-                const float4 v = ld_vec<float4>(A + (int64_t)gr * lda + gk);
+    for (int q = 0; q < C_::A_PER; ++q) {
+        const int L = tid + q * C_::NTHR;
+        a_off[q] = (int64_t)(m0 + L / (KT / 4)) * lda + (L % (KT / 4)) * 4;
+    }
+#pragma unroll
+    for (int q = 0; q < C_::B_PER; ++q) {
+        const int L = tid + q * C_::NTHR;
+        b_off[q] = (int64_t)(KPACK * (L / (NT / BV))) * ldb + n0 + (L % (NT / BV)) * BV;
+    }
+    // a tile wholly inside the window: full slices need no bounds checks
+    const bool full_tile = m0 + MT <= M && n0 + NT <= N;
+
+    auto load_slice = [&](int k0) {
+        const T* As0 = A + k0;
+        if (VEC && full_tile && k0 + KT <= kend) {
+            // uniform branch: every lane loads whole vectors
+#pragma unroll
+            for (int q = 0; q < C_::A_PER; ++q) {
+                const float4 v = ld_vec<float4>(As0 + a_off[q]);
                 ra[q][0] = __builtin_bit_cast(T, v.x);
                 ra[q][1] = __builtin_bit_cast(T, v.y);
                 ra[q][2] = __builtin_bit_cast(T, v.z);
                 ra[q][3] = __builtin_bit_cast(T, v.w);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    ra[q][e] = (gr < M && gk + e < kend) ? A[(int64_t)gr * lda + gk + e] : S::inf();
             }
-        }
-#pragma unroll
-        for (int q = 0; q < C_::B_PER; ++q) {
-            const int L = tid + q * C_::NTHR;
-            const int p = L / (NT / BV);
-            const int cv = L % (NT / BV);
-            const int gc = n0 + cv * BV;
 #pragma unroll
             for (int h = 0; h < KPACK; ++h) {
-                const int gk = k0 + KPACK * p + h;
-                if constexpr (BV == 4) {
-                    if (VEC && gk < kend && gc + 3 < N) {
-                        const float4 v = ld_vec<float4>(B + (int64_t)gk * ldb + gc);
+                const T* Bs0 = B + (int64_t)(k0 + h) * ldb;
+#pragma unroll
+                for (int q = 0; q < C_::B_PER; ++q) {
+                    if constexpr (BV == 4) {
+                        const float4 v = ld_vec<float4>(Bs0 + b_off[q]);
                         rb[q][h][0] = __builtin_bit_cast(T, v.x);
                         rb[q][h][1] = __builtin_bit_cast(T, v.y);
                         rb[q][h][2] = __builtin_bit_cast(T, v.z);
                         rb[q][h][3] = __builtin_bit_cast(T, v.w);
-                        continue;
-                    }
-                } else {
-                    if (VEC && gk < kend && gc + 1 < N) {
-                        const Pair2<T> v = ld_vec<Pair2<T>>(B + (int64_t)gk * ldb + gc);
+                    } else {
+                        const Pair2<T> v = ld_vec<Pair2<T>>(Bs0 + b_off[q]);
                         rb[q][h][0] = v.x;
                         rb[q][h][1] = v.y;
-                        continue;
                     }
                 }
+            }
+            return;
+        }
+        // edge tiles and the last partial slice: every element checked
 #pragma unroll
-                for (int e = 0; e < BV; ++e)
-                    rb[q][h][e] = (gk < kend && gc + e < N) ? B[(int64_t)gk * ldb + gc + e] : S::inf();
+        for (int q = 0; q < C_::A_PER; ++q) {
+            const int L = tid + q * C_::NTHR;
+            const bool row_ok = m0 + L / (KT / 4) < M;
+            const int gk = k0 + (L % (KT / 4)) * 4;
+            const T* src = As0 + a_off[q];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ra[q][e] = (row_ok && gk + e < kend) ? src[e] : S::inf();
+        }
+#pragma unroll
+        for (int h = 0; h < KPACK; ++h) {
+            const T* Bs0 = B + (int64_t)(k0 + h) * ldb;
+#pragma unroll
+            for (int q = 0; q < C_::B_PER; ++q) {
+                const int L = tid + q * C_::NTHR;
+                const int gk = k0 + KPACK * (L / (NT / BV)) + h;
+                const int gc = n0 + (L % (NT / BV)) * BV;
+                const T* src = Bs0 + b_off[q];
+#pragma unroll
+                for (int e = 0; e < BV; ++e) rb[q][h][e] = (gk < kend && gc + e < N) ? src[e] : S::inf();
             }
         }
     };
