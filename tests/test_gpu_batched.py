@@ -80,6 +80,24 @@ def test_batched_graph_replays_and_buffer_swaps(native, dev, persistent):
             np.testing.assert_array_equal(got, ref, err_msg=f"replay {rep}")
 
 
+def test_batched_one_launch_plans_and_plan_switches(native, dev):
+    # every graph n <= 128: the lock-step plan is one closure launch, issued
+    # directly; alternating it with a multi-launch batch on the same context
+    # switches between the direct launch and the captured graph
+    rng = np.random.default_rng(903)
+    small = [rand_graph(rng, n, min(0.5, 4.0 / max(n, 1))) for n in (0, 1, 2, 17, 64, 100, 127, 128, 5)]
+    mixed = [rand_graph(rng, n, 0.05) for n in (90, 300, 129, 40)]
+    cases = [(small, [oracle.fw_i32(W) for W in small]), (mixed, [oracle.fw_i32(W) for W in mixed])]
+    bufs = {id(m): [pack(m, dev) for _ in range(2)] for m, _ in cases}
+    for rep in range(6):
+        mats, refs = cases[rep % 2]
+        flat, off_d, sz_d, hs, off = bufs[id(mats)][(rep // 2) % 2]
+        flat.copy_(torch.from_numpy(gg.pack_batch(mats)[0]).to(dev))
+        native.apsp_batched(flat, off_d, sz_d, hs)
+        for ref, got in zip(refs, unpack(flat, off, hs)):
+            np.testing.assert_array_equal(got, ref, err_msg=f"call {rep}")
+
+
 @pytest.mark.parametrize("persistent", [False, True])
 def test_batched_workload_512(native, dev, persistent):
     batch = gg.batch_ragged()
