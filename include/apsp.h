@@ -315,6 +315,18 @@ apsp_status_t apsp_costmodel_set_norm(apsp_ctx_t *ctx, const float *h_mu4, const
 /* Copies count = 4480 + 65 K floats in / out (host memory); set resets Adam. */
 apsp_status_t apsp_costmodel_set_params(apsp_ctx_t *ctx, const float *h_params, int64_t count);
 apsp_status_t apsp_costmodel_get_params(apsp_ctx_t *ctx, float *h_params, int64_t count);
+/* Model file I/O (plain text, so a trained model moves between processes
+ * and languages): "apsp-costmodel 1", then K, the layer sizes, the four
+ * feature means and deviations and the 4480 + 65 K parameters, every value
+ * printed with 9 significant digits (binary32 reads back exactly).  Save
+ * waits for the device and needs a model; load parses and checks the whole
+ * file (header, sizes equal to this library's, finite values, deviations
+ * > 0) before it changes the context, then initialises a model of that K if
+ * needed and sets the standardisation and parameters (Adam state reset).
+ * APSP_E_ARG for a NULL path, a file that cannot be opened or written, or a
+ * malformed file (the context is then unchanged). */
+apsp_status_t apsp_costmodel_save(apsp_ctx_t *ctx, const char *path);
+apsp_status_t apsp_costmodel_load(apsp_ctx_t *ctx, const char *path);
 /* d_X rows x 4, d_T and d_mask rows x K (mask 1 = target present).  d_losses
  * (steps floats, may be NULL) receives the loss before each step. */
 apsp_status_t apsp_costmodel_train(apsp_ctx_t *ctx, const float *d_X, const float *d_T, const float *d_mask,

@@ -34,7 +34,8 @@ EXPORTS = [
     "minplus_gemm", "apsp_closure", "apsp_fw", "apsp_rkleene", "apsp_square",
     "apsp_solve", "apsp_batched", "apsp_validate", "apsp_profile_enable", "apsp_profile_read",
     "apsp_candidate_count", "apsp_candidate", "apsp_costmodel_init", "apsp_costmodel_set_norm",
-    "apsp_costmodel_set_params", "apsp_costmodel_get_params", "apsp_costmodel_train", "apsp_costmodel_grad",
+    "apsp_costmodel_set_params", "apsp_costmodel_get_params", "apsp_costmodel_save", "apsp_costmodel_load",
+    "apsp_costmodel_train", "apsp_costmodel_grad",
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
     "apsp_packed16_counts", "apsp_predecessors_ex",
 ]
@@ -120,6 +121,8 @@ def lib() -> ctypes.CDLL:
             L.apsp_costmodel_set_norm.argtypes = [vp, f32p, f32p]
             L.apsp_costmodel_set_params.argtypes = [vp, f32p, i64]
             L.apsp_costmodel_get_params.argtypes = [vp, f32p, i64]
+            L.apsp_costmodel_save.argtypes = [vp, ctypes.c_char_p]
+            L.apsp_costmodel_load.argtypes = [vp, ctypes.c_char_p]
             L.apsp_costmodel_train.argtypes = [vp, vp, vp, vp, i32, P(TrainCfg), vp, vp]
             L.apsp_costmodel_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
             L.apsp_costmodel_forward.argtypes = [vp, vp, i32, vp, vp]
@@ -382,6 +385,16 @@ def apsp_costmodel_get_params(K: int, device: int | None = None):
     a = np.empty(mlp_param_count(K), dtype=np.float32)
     _check(lib().apsp_costmodel_get_params(context(device), a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
     return a
+
+
+def apsp_costmodel_save(path, device: int | None = None):
+    """Writes the context's model to a text file (apsp_costmodel_save)."""
+    _check(lib().apsp_costmodel_save(context(device), os.fsencode(path)))
+
+
+def apsp_costmodel_load(path, device: int | None = None):
+    """Reads a model file into the context (apsp_costmodel_load)."""
+    _check(lib().apsp_costmodel_load(context(device), os.fsencode(path)))
 
 
 def apsp_costmodel_train(X, T, mask, steps=500, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, losses=None, stream=None):

@@ -4,6 +4,7 @@
     python -m paper_2310_03983_amd.autotune train --db timings.json --model model.json
     python -m paper_2310_03983_amd.autotune evaluate --db timings.json --model model.json
     python -m paper_2310_03983_amd.autotune batch --db batch_timings.json
+    python -m paper_2310_03983_amd.autotune export --model model.json --out model.txt
 
 `sweep` times every candidate plan of the library (apsp_candidate) on every
 graph of the 200-graph sweep workload (n log-uniform in [64, 32768], p
@@ -24,6 +25,7 @@ the best single static candidate and the library's size rule.
 lock-step direct launches, persistent kernel, one launch per graph) on the
 512-graph ragged batch and on each size class of it, checks that they agree,
 and writes the winner per class.
+`export` writes a trained model in the text format of apsp_costmodel_load.
 """
 from __future__ import annotations
 
@@ -275,6 +277,18 @@ def install(model):
     apsp.apsp_costmodel_set_params(np.asarray(model["params"], dtype=np.float32))
 
 
+def export_text(model, path):
+    """Writes a trained model (the JSON dict of `train`) in the text format
+    apsp_costmodel_load reads, so C callers can plan without Python."""
+    f32 = lambda v: "%.9g" % float(np.float32(v))
+    params = np.asarray(model["params"], dtype=np.float32)
+    lines = ["apsp-costmodel 1", f"K {model['K']}", "in 4", "hidden 64",
+             "mu " + " ".join(f32(v) for v in model["mu"]), "sd " + " ".join(f32(v) for v in model["sd"]),
+             f"params {params.size}"] + [f32(v) for v in params]
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def predict(model, X):
     import torch
     from . import apsp
@@ -324,14 +338,21 @@ def evaluate(db, model, test_ids, train_ids):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["sweep", "train", "evaluate", "batch"])
-    ap.add_argument("--db", required=True)
+    ap.add_argument("cmd", choices=["sweep", "train", "evaluate", "batch", "export"])
+    ap.add_argument("--out", help="export: path of the text model file")
+    ap.add_argument("--db")
     ap.add_argument("--model")
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--last", type=int, default=199)
     ap.add_argument("--train-count", type=int, default=150)
     ap.add_argument("--steps", type=int, default=3000)
     a = ap.parse_args(argv)
+    if a.cmd == "export":
+        with open(a.model) as f:
+            export_text(json.load(f), a.out)
+        return 0
+    if not a.db:
+        ap.error("--db is required for " + a.cmd)
     if a.cmd == "sweep":
         sweep(a.db, a.first, a.last, progress=lambda m: print(m, flush=True))
         return 0

@@ -1307,6 +1307,76 @@ apsp_status_t apsp_costmodel_get_params(apsp_ctx_t* ctx, float* h, int64_t count
     return APSP_OK;
 }
 
+apsp_status_t apsp_costmodel_save(apsp_ctx_t* ctx, const char* path)
+{
+    apsp_status_t rc;
+    if (!path) return fail(APSP_E_ARG, "NULL path");
+    if ((rc = check_ctx(ctx)) || (rc = check_model(ctx))) return rc;
+    const int K = ctx->cm_K;
+    const int np = apsp::mlp_param_count(K);
+    std::vector<float> h(np);
+    HIP_TRY(hipDeviceSynchronize(), "costmodel sync");
+    HIP_TRY(hipMemcpy(h.data(), ctx->cm_params, (size_t)np * 4, hipMemcpyDeviceToHost), "params download");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(APSP_E_ARG, "cannot open %s for writing", path);
+    // %.9g prints every binary32 value so that it reads back exactly
+    std::fprintf(f, "apsp-costmodel 1\nK %d\nin %d\nhidden %d\nmu", K, apsp::kMlpIn, apsp::kMlpHidden);
+    for (int i = 0; i < apsp::kMlpIn; ++i) std::fprintf(f, " %.9g", (double)ctx->cm_norm.mu[i]);
+    std::fprintf(f, "\nsd");
+    for (int i = 0; i < apsp::kMlpIn; ++i) std::fprintf(f, " %.9g", (double)ctx->cm_norm.sd[i]);
+    std::fprintf(f, "\nparams %d\n", np);
+    for (int i = 0; i < np; ++i) std::fprintf(f, "%.9g\n", (double)h[i]);
+    const bool ok = !std::ferror(f);
+    if (std::fclose(f) != 0 || !ok) return fail(APSP_E_ARG, "writing %s failed", path);
+    return APSP_OK;
+}
+
+apsp_status_t apsp_costmodel_load(apsp_ctx_t* ctx, const char* path)
+{
+    if (!path) return fail(APSP_E_ARG, "NULL path");
+    // parse and check the whole file before touching the context
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(APSP_E_ARG, "cannot open %s", path);
+    char tag[32] = {0};
+    int ver = 0, K = 0, in = 0, hidden = 0, np = -1;
+    float mu[apsp::kMlpIn], sd[apsp::kMlpIn];
+    std::vector<float> h;
+    const char* bad = nullptr;
+    auto word = [&](const char* w) {
+        char got[32] = {0};
+        return std::fscanf(f, "%31s", got) == 1 && std::strcmp(got, w) == 0;
+    };
+    if (std::fscanf(f, "%31s %d", tag, &ver) != 2 || std::strcmp(tag, "apsp-costmodel") != 0 || ver != 1)
+        bad = "header is not 'apsp-costmodel 1'";
+    else if (!word("K") || std::fscanf(f, "%d", &K) != 1 || K < 1 || K > 64)
+        bad = "K missing or outside 1..64";
+    else if (!word("in") || std::fscanf(f, "%d", &in) != 1 || in != apsp::kMlpIn ||
+             !word("hidden") || std::fscanf(f, "%d", &hidden) != 1 || hidden != apsp::kMlpHidden)
+        bad = "layer sizes differ from this library's";
+    if (!bad) {
+        bool ok = word("mu");
+        for (int i = 0; ok && i < apsp::kMlpIn; ++i) ok = std::fscanf(f, "%f", &mu[i]) == 1 && std::isfinite(mu[i]);
+        ok = ok && word("sd");
+        for (int i = 0; ok && i < apsp::kMlpIn; ++i) ok = std::fscanf(f, "%f", &sd[i]) == 1 && sd[i] > 0.f;
+        if (!ok) bad = "mu / sd missing, not finite, or sd not positive";
+    }
+    if (!bad && (!word("params") || std::fscanf(f, "%d", &np) != 1 || np != apsp::mlp_param_count(K)))
+        bad = "parameter count differs from the model size";
+    if (!bad) {
+        h.resize(np);
+        for (int i = 0; i < np && !bad; ++i)
+            if (std::fscanf(f, "%f", &h[i]) != 1 || !std::isfinite(h[i])) bad = "parameter missing or not finite";
+    }
+    std::fclose(f);
+    if (bad) return fail(APSP_E_ARG, "%s: malformed cost model file (%s)", path, bad);
+    apsp_status_t rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!ctx->cm_params || ctx->cm_K != K)
+        if ((rc = apsp_costmodel_init(ctx, K, 0))) return rc;
+    if ((rc = apsp_costmodel_set_norm(ctx, mu, sd))) return rc;
+    return apsp_costmodel_set_params(ctx, h.data(), np);
+}
+
 apsp_status_t apsp_costmodel_train(apsp_ctx_t* ctx, const float* X, const float* T, const float* M, int32_t rows,
                                    const apsp_train_cfg_t* cfg, float* losses, void* stream)
 {

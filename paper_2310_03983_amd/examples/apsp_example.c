@@ -2,12 +2,14 @@
  * apsp_example.c -- drives libapsp through its C ABI only (no Python, no
  * torch): builds a small directed graph, solves it with blocked
  * Floyd-Warshall and R-Kleene, recovers one shortest path from the
- * predecessor matrix and prints it.
+ * predecessor matrix and prints it.  Given a cost-model file (the text
+ * format of apsp_costmodel_load, e.g. data/costmodel_mlp.txt), it also
+ * loads the model and prints the plan it picks for a large sparse graph.
  *
  *   cc -I include paper_2310_03983_amd/examples/apsp_example.c \
  *      -L paper_2310_03983_amd -lapsp -L /opt/rocm/lib -lamdhip64 \
  *      -Wl,-rpath,paper_2310_03983_amd -Wl,-rpath,/opt/rocm/lib -o apsp_example
- *   ./apsp_example            (needs a GPU; exit status 0 on success)
+ *   ./apsp_example [model.txt]    (needs a GPU; exit status 0 on success)
  *
  * Device memory comes straight from the HIP runtime (hipMalloc/hipMemcpy are
  * declared below so that the example needs no HIP headers).
@@ -38,7 +40,7 @@ static int check(apsp_status_t st, const char *what)
     return 0;
 }
 
-int main(void)
+int main(int argc, char **argv)
 {
     /* 0 -> 1 -> 2 -> 3 -> 4 -> 5 chain of cost 1 plus a costly shortcut 0 -> 5 */
     int32_t W[N * N];
@@ -82,6 +84,17 @@ int main(void)
     for (int t = len - 1; t >= 0; --t) printf(" %d", path[t]);
     printf("\n");
     ok &= (len == N);
+
+    if (argc > 1) {
+        /* the trained cost model picks the plan apsp_solve would run */
+        apsp_opts_t plan;
+        int32_t choice = -1;
+        if (check(apsp_costmodel_load(ctx, argv[1]), "apsp_costmodel_load")) return 1;
+        if (check(apsp_plan(ctx, APSP_I32, 16384, 0.01, 1, 1, &plan, &choice), "apsp_plan")) return 1;
+        printf("plan for n=16384, density 0.01: candidate %d (algo %d, block %d, cutover %d, flags %d)\n",
+               (int)choice, (int)plan.algo, (int)plan.block, (int)plan.cutover, (int)plan.flags);
+        ok &= (choice >= 0);
+    }
 
     hipFree(dW); hipFree(dD); hipFree(dP);
     apsp_destroy(ctx);

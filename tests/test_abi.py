@@ -196,3 +196,60 @@ def test_predecessors_ex_argument_errors(native):
         native.APSP_E_UNSUPPORTED
     assert f(None, 0, 4, D, 4, W, 4, P, 4, native.PRED["sparse"], None) == native.APSP_E_ARG
     assert "context" in native.last_error()
+
+
+def _model_text(K=3, mu=(0.0, 1.0, 2.0, 3.0), sd=(1.0, 1.0, 0.5, 2.0), params=None, count=None):
+    n = 4480 + 65 * K
+    vals = params if params is not None else [0.001 * i for i in range(n)]
+    lines = ["apsp-costmodel 1", f"K {K}", "in 4", "hidden 64",
+             "mu " + " ".join(repr(float(x)) for x in mu), "sd " + " ".join(repr(float(x)) for x in sd),
+             f"params {n if count is None else count}"] + [repr(float(v)) for v in vals]
+    return "\n".join(lines) + "\n"
+
+
+def test_costmodel_file_checks_before_the_context(native, tmp_path):
+    """apsp_costmodel_load parses and checks the whole file before it looks at
+    the context: malformed files fail with their reason even with a NULL
+    context, a well-formed one then fails only on the NULL context."""
+    L = native.lib()
+    assert L.apsp_costmodel_load(None, None) == native.APSP_E_ARG and "NULL path" in native.last_error()
+    assert L.apsp_costmodel_load(None, os.fsencode(str(tmp_path / "missing.txt"))) == native.APSP_E_ARG
+    assert "cannot open" in native.last_error()
+    good = _model_text()
+    bad_cases = {
+        "header": good.replace("apsp-costmodel 1", "apsp-costmodel 2"),
+        "K missing or outside": good.replace("K 3", "K 65"),
+        "layer sizes": good.replace("hidden 64", "hidden 32"),
+        "sd not positive": _model_text(sd=(1.0, 0.0, 1.0, 1.0)),
+        "mu / sd missing, not finite": _model_text(mu=(0.0, float("nan"), 0.0, 0.0)),
+        "parameter count": _model_text(count=4480 + 65 * 3 - 1),
+        "parameter missing": "\n".join(good.splitlines()[:-5]) + "\n",
+        "not finite": _model_text(params=[0.0] * (4480 + 195 - 1) + [float("inf")]),
+    }
+    for reason, text in bad_cases.items():
+        p = tmp_path / "m.txt"
+        p.write_text(text)
+        assert L.apsp_costmodel_load(None, os.fsencode(str(p))) == native.APSP_E_ARG, reason
+        msg = native.last_error()
+        assert "malformed" in msg and reason in msg, (reason, msg)
+    p = tmp_path / "good.txt"
+    p.write_text(good)
+    assert L.apsp_costmodel_load(None, os.fsencode(str(p))) == native.APSP_E_ARG
+    assert "context is NULL" in native.last_error()
+    assert L.apsp_costmodel_save(None, os.fsencode(str(p))) == native.APSP_E_ARG
+    assert L.apsp_costmodel_save(None, None) == native.APSP_E_ARG
+
+
+def test_shipped_model_text_matches_its_json():
+    """data/costmodel_mlp.txt (written by `autotune export`) holds exactly the
+    binary32 values of data/costmodel_mlp.json."""
+    import json
+    import numpy as np
+    data = os.path.join(ROOT, "paper_2310_03983_amd", "data")
+    model = json.load(open(os.path.join(data, "costmodel_mlp.json")))
+    lines = open(os.path.join(data, "costmodel_mlp.txt")).read().split("\n")
+    assert lines[:4] == ["apsp-costmodel 1", f"K {model['K']}", "in 4", "hidden 64"]
+    np.testing.assert_array_equal(np.float32(lines[4].split()[1:]), np.float32(model["mu"]))
+    np.testing.assert_array_equal(np.float32(lines[5].split()[1:]), np.float32(model["sd"]))
+    assert lines[6] == f"params {len(model['params'])}"
+    np.testing.assert_array_equal(np.float32(lines[7:7 + len(model["params"])]), np.float32(model["params"]))

@@ -193,3 +193,33 @@ def test_trained_model_gain_on_held_out_graphs(native, dev):
     shipped = json.load(open(os.path.join(os.path.dirname(autotune.__file__), "data", "costmodel_mlp.json")))
     ev2 = autotune.evaluate(db, shipped, test_ids, train_ids)
     assert ev2["mlp"]["mean_regret"] < ev2["static_best"]["mean_regret"]
+
+
+def test_costmodel_file_round_trip(native, dev, tmp_path):
+    """apsp_costmodel_save / apsp_costmodel_load: a model written to a file and
+    read into a context holding a different model comes back bit for bit
+    (parameters and standardisation), and plans the same."""
+    import json
+    import os
+    from paper_2310_03983_amd import autotune
+    model = json.load(open(os.path.join(os.path.dirname(autotune.__file__), "data", "costmodel_mlp.json")))
+    autotune.install(model)
+    K = model["K"]
+    p0 = native.apsp_costmodel_get_params(K)
+    probes = [(16384, 0.01), (2048, 0.3), (300, 0.01), (8192, 0.001), (100, 0.5)]
+    plans0 = [native.apsp_plan(n, d)[1] for n, d in probes]
+    path = tmp_path / "model.txt"
+    native.apsp_costmodel_save(str(path))
+    text = path.read_text().splitlines()
+    assert text[0] == "apsp-costmodel 1" and text[1] == f"K {K}"
+    native.apsp_costmodel_init(5, 123)           # a different model in the context
+    native.apsp_costmodel_load(str(path))
+    np.testing.assert_array_equal(native.apsp_costmodel_get_params(K), p0)
+    assert [native.apsp_plan(n, d)[1] for n, d in probes] == plans0
+    # a malformed file leaves the loaded model in place
+    bad = tmp_path / "bad.txt"
+    bad.write_text("\n".join(text[:-3]) + "\n")
+    with pytest.raises(native.ApspError) as e:
+        native.apsp_costmodel_load(str(bad))
+    assert e.value.status == native.APSP_E_ARG
+    np.testing.assert_array_equal(native.apsp_costmodel_get_params(K), p0)
