@@ -14,6 +14,9 @@ Reported alongside the headline:
                   tiles): algorithmic VALU ops (2 per min-plus term: one add,
                   one min) per launch / its average launch duration, timed
                   with HIP events on the launch stream during the timed steps;
+  panel_phase  -- the FW panel products (64 x 64 tiles, K = 128) of the same
+                  solve: compulsory HBM bytes / event-timed duration, GB/s
+                  against the 8 TB/s HBM peak (recorded in one more solve);
   cpu_baseline -- the CPU oracle (per-source Dijkstra, OpenMP over sources)
                   on a bounded sample of sources of the same graph,
                   extrapolated to the full APSP.
@@ -58,6 +61,9 @@ def parse():
                     help="time the solve with APSP_FLAG_PACKED16 (int32 in and out, products in capped 16-bit "
                          "arithmetic) instead of the int32 products")
     return ap.parse_args()
+
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 
 def log(msg):
@@ -316,6 +322,14 @@ def main():
                                                       ("minplus_64", apsp.KERNEL_MINPLUS_64),
                                                       ("closure", apsp.KERNEL_CLOSURE))}
     apsp.apsp_profile_enable(False)
+    # panel phase: the 64x64 products of the FW windows (row and column
+    # panels, look-ahead band updates), recorded alone in one more solve
+    share_in.copy_(Wd)
+    apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_64])
+    solve(share_in, cutover=args.cutover)
+    torch.cuda.synchronize()
+    k64 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_64)
+    apsp.apsp_profile_enable(False)
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = n ** 3 / (ms_per_step / 1e3)
@@ -362,6 +376,19 @@ def main():
                     ("achieved: 2 algorithmic ops per min-plus term (add + min); peak: 39.32e12 VALU "
                      "lane-instructions/s x the 2 ops one lane-instruction of the fold performs (one 64-bit add "
                      "forms two 32-bit sums, one v_min3_u32 takes two minima)"),
+        },
+        "panel_phase": {
+            "kernel": "k_minplus<int32, 64x64 tile>" + (" (capped 16-bit)" if args.packed16 else ""),
+            "what": "FW panel products of the 4096 windows: row and column panels, look-ahead band updates (K = 128)",
+            "launches_per_solve": k64["launches"],
+            "ms_per_solve": k64["ms"],
+            "bytes_per_launch": k64["bytes"] / max(k64["launches"], 1),
+            "achieved": k64["bytes"] / max(k64["ms"], 1e-9) / 1e6,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": k64["bytes"] / max(k64["ms"], 1e-9) / 1e6 / HBM_PEAK_GBS,
+            "note": "compulsory bytes (operands read once, C read and written once) / event-timed duration; "
+                    "each launch is one short round of tiles, so it is latency-bound, not HBM-bound",
         },
         "kernel_ms_per_solve": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in shares.items()},
     }
