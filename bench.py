@@ -14,6 +14,10 @@ Reported alongside the headline:
                   tiles): algorithmic VALU ops (2 per min-plus term: one add,
                   one min) per launch / its average launch duration, timed
                   with HIP events on the launch stream during the timed steps;
+  measured_ceiling -- the same kernel's achieved rate against the fold's
+                  issue rate measured by a spin kernel on the device (and that
+                  rate per lane and ns: the clock, at one lane-instruction per
+                  cycle);
   panel_phase  -- the FW panel products (64 x 64 tiles, K = 128) of the same
                   solve: compulsory HBM bytes / event-timed duration, GB/s
                   against the 8 TB/s HBM peak (recorded in one more solve);
@@ -331,6 +335,9 @@ def main():
     k64 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_64)
     apsp.apsp_profile_enable(False)
 
+    # the fold's issue rate on this device now (spin kernel), beside the nominal peak
+    fold_rate = apsp.apsp_measure_fold_rate("packed16" if args.packed16 else "int32")
+
     ms_per_step = elapsed * 1e3 / args.steps
     value = n ** 3 / (ms_per_step / 1e3)
     avg_ms = k128["ms"] / max(k128["launches"], 1)
@@ -377,6 +384,15 @@ def main():
                      "lane-instructions/s x the 2 ops one lane-instruction of the fold performs (one 64-bit add "
                      "forms two 32-bit sums, one v_min3_u32 takes two minima)"),
         },
+        "measured_ceiling": {
+            "what": "spin kernel repeating the fold's own instructions on registers over the whole device "
+                    "(apsp_measure_fold_rate), run after the timed steps",
+            "terms_per_s": fold_rate["terms_per_s"],
+            "lane_instr_per_s": fold_rate["lane_instr_per_s"],
+            # equals the clock in GHz when the fold issues one lane-instruction per lane and cycle
+            "lane_instr_per_lane_per_ns": fold_rate["lane_instr_per_s"] / (256 * 64) / 1e9,
+            "frac": achieved / (2.0 * fold_rate["terms_per_s"]),
+        },
         "panel_phase": {
             "kernel": "k_minplus<int32, 64x64 tile>" + (" (capped 16-bit)" if args.packed16 else ""),
             "what": "FW panel products of the 4096 windows: row and column panels, look-ahead band updates (K = 128)",
@@ -409,6 +425,7 @@ def main():
             torch.cuda.empty_cache()
         extras["rkleene_i32_packed16"] = bench_packed16(torch, apsp, Wd, n, args.cutover)
         extras.update(bench_small(torch, apsp, gg, dev))
+        extras["fold_rates"] = {k: apsp.apsp_measure_fold_rate(k) for k in ("int32", "float32", "packed16")}
         if Wd.dtype == torch.int32:
             # last-hop predecessors of the timed graph (sparse form: n * m candidates)
             Dn = Wd.clone()

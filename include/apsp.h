@@ -376,6 +376,25 @@ typedef struct apsp_kernel_stats {
 apsp_status_t apsp_profile_enable(apsp_ctx_t *ctx, int32_t on);
 apsp_status_t apsp_profile_read(apsp_ctx_t *ctx, int32_t kind, apsp_kernel_stats_t *out);
 
+/*
+ * Issue-rate calibration for measurement tools (Sec. 3, Eq. 2: the fold is
+ * the product's inner step).  Runs a spin kernel over the whole device in
+ * which every lane repeats the fold's own instructions on registers, with
+ * independent chains so nothing waits: APSP_FOLD_I32 (one 64-bit add for two
+ * sums, one v_min3_u32), APSP_FOLD_F32 (two v_add_f32, one v_min3_f32),
+ * APSP_FOLD_PACKED16 (one 64-bit add for four 16-bit sums, one
+ * v_pk_minimum3_f16).  Synchronous on `stream` (a warm-up launch, then one
+ * event-timed launch of roughly 10-20 ms); writes the achieved min-plus
+ * terms/s and VALU lane-instructions/s -- the ceiling the product kernels
+ * can reach at the clock the device runs now.  Touches one word of the
+ * context's scratch.  APSP_E_ARG for an unknown fold or NULL outputs.
+ */
+#define APSP_FOLD_I32      0
+#define APSP_FOLD_F32      1
+#define APSP_FOLD_PACKED16 2
+apsp_status_t apsp_measure_fold_rate(apsp_ctx_t *ctx, int32_t fold, void *stream, double *h_terms_per_s,
+                                     double *h_lane_instr_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,8 +37,9 @@ EXPORTS = [
     "apsp_costmodel_set_params", "apsp_costmodel_get_params", "apsp_costmodel_save", "apsp_costmodel_load",
     "apsp_costmodel_train", "apsp_costmodel_grad",
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
-    "apsp_packed16_counts", "apsp_predecessors_ex",
+    "apsp_packed16_counts", "apsp_predecessors_ex", "apsp_measure_fold_rate",
 ]
+FOLD = {"int32": 0, "float32": 1, "packed16": 2}
 PRED = {"auto": 0, "dense": 1, "sparse": 2}
 
 KERNEL_MINPLUS_128, KERNEL_MINPLUS_64, KERNEL_CLOSURE, KERNEL_OTHER = 0, 1, 2, 3
@@ -121,6 +122,7 @@ def lib() -> ctypes.CDLL:
             L.apsp_costmodel_set_norm.argtypes = [vp, f32p, f32p]
             L.apsp_costmodel_set_params.argtypes = [vp, f32p, i64]
             L.apsp_costmodel_get_params.argtypes = [vp, f32p, i64]
+            L.apsp_measure_fold_rate.argtypes = [vp, i32, vp, P(ctypes.c_double), P(ctypes.c_double)]
             L.apsp_costmodel_save.argtypes = [vp, ctypes.c_char_p]
             L.apsp_costmodel_load.argtypes = [vp, ctypes.c_char_p]
             L.apsp_costmodel_train.argtypes = [vp, vp, vp, vp, i32, P(TrainCfg), vp, vp]
@@ -385,6 +387,17 @@ def apsp_costmodel_get_params(K: int, device: int | None = None):
     a = np.empty(mlp_param_count(K), dtype=np.float32)
     _check(lib().apsp_costmodel_get_params(context(device), a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
     return a
+
+
+def apsp_measure_fold_rate(fold: str = "int32", device: int | None = None, stream=None) -> dict:
+    """Spin-kernel issue rate of a fold ("int32", "float32", "packed16"):
+    {"terms_per_s", "lane_instr_per_s"} (apsp_measure_fold_rate)."""
+    t, li = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    dev = torch.cuda.current_device() if device is None else device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib().apsp_measure_fold_rate(context(dev), FOLD[fold], ctypes.c_void_p(st.cuda_stream),
+                                        ctypes.byref(t), ctypes.byref(li)))
+    return {"terms_per_s": t.value, "lane_instr_per_s": li.value}
 
 
 def apsp_costmodel_save(path, device: int | None = None):

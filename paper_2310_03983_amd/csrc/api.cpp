@@ -1307,6 +1307,39 @@ apsp_status_t apsp_costmodel_get_params(apsp_ctx_t* ctx, float* h, int64_t count
     return APSP_OK;
 }
 
+apsp_status_t apsp_measure_fold_rate(apsp_ctx_t* ctx, int32_t fold, void* stream, double* h_terms_per_s,
+                                     double* h_lane_instr_per_s)
+{
+    apsp_status_t rc;
+    if (fold < APSP_FOLD_I32 || fold > APSP_FOLD_PACKED16) return fail(APSP_E_ARG, "fold = %d", fold);
+    if (!h_terms_per_s || !h_lane_instr_per_s) return fail(APSP_E_ARG, "NULL output");
+    if ((rc = check_ctx(ctx))) return rc;
+    const apsp::DType dt = fold == APSP_FOLD_F32 ? apsp::F32 : fold == APSP_FOLD_PACKED16 ? apsp::I32P16 : apsp::I32;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = ctx->num_cus * 8;   // eight 4-wave workgroups per CU: 8 waves per SIMD
+    const int iters = 65536;
+    uint32_t* sink = static_cast<uint32_t*>(ctx->d_scratch) + 32;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = apsp::launch_fold_spin(dt, grid, iters / 16, 1u, sink, st);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = apsp::launch_fold_spin(dt, grid, iters, 2u, sink, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "fold-rate spin");
+    if (!(ms > 0.f)) return fail(APSP_E_HIP, "fold-rate spin: no elapsed time");
+    const apsp::FoldSpin f = apsp::fold_spin_shape(dt);
+    const double lanes = (double)grid * apsp::fold_spin_threads() * iters;
+    *h_terms_per_s = lanes * f.terms / (ms * 1e-3);
+    *h_lane_instr_per_s = lanes * f.instr / (ms * 1e-3);
+    return APSP_OK;
+}
+
 apsp_status_t apsp_costmodel_save(apsp_ctx_t* ctx, const char* path)
 {
     apsp_status_t rc;

@@ -73,6 +73,16 @@ hipError_t launch_count_ge(const uint32_t* D, int64_t n, int64_t ld, uint32_t th
 // Fill kernel used instead of hipMemsetAsync for small device counters.
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
 
+// Issue-rate calibration: a spin kernel running the fold of `dt` (I32P16 =
+// the capped 16-bit fold) for `iters` iterations per lane on registers.
+struct FoldSpin {
+    int instr;   // fold instructions per iteration and lane
+    int terms;   // min-plus terms per iteration and lane
+};
+FoldSpin fold_spin_shape(DType dt);
+int fold_spin_threads();
+hipError_t launch_fold_spin(DType dt, int grid, int iters, uint32_t seed, uint32_t* sink, hipStream_t st);
+
 // One min-plus squaring pass D <- min(D, D (min,+) D) with change detection:
 // *d_changed is set to 1 when any entry decreased.
 hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld,

@@ -253,3 +253,13 @@ def test_shipped_model_text_matches_its_json():
     np.testing.assert_array_equal(np.float32(lines[5].split()[1:]), np.float32(model["sd"]))
     assert lines[6] == f"params {len(model['params'])}"
     np.testing.assert_array_equal(np.float32(lines[7:7 + len(model["params"])]), np.float32(model["params"]))
+
+
+def test_fold_rate_argument_errors(native):
+    L = native.lib()
+    t, li = ctypes.c_double(), ctypes.c_double()
+    assert L.apsp_measure_fold_rate(None, 3, None, ctypes.byref(t), ctypes.byref(li)) == native.APSP_E_ARG
+    assert "fold" in native.last_error()
+    assert L.apsp_measure_fold_rate(None, 0, None, None, ctypes.byref(li)) == native.APSP_E_ARG
+    assert L.apsp_measure_fold_rate(None, 0, None, ctypes.byref(t), ctypes.byref(li)) == native.APSP_E_ARG
+    assert "context is NULL" in native.last_error()

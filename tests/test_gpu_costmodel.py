@@ -223,3 +223,4 @@ def test_costmodel_file_round_trip(native, dev, tmp_path):
         native.apsp_costmodel_load(str(bad))
     assert e.value.status == native.APSP_E_ARG
     np.testing.assert_array_equal(native.apsp_costmodel_get_params(K), p0)
+
