@@ -26,6 +26,8 @@ lock-step direct launches, persistent kernel, one launch per graph) on the
 512-graph ragged batch and on each size class of it, checks that they agree,
 and writes the winner per class.
 `export` writes a trained model in the text format of apsp_costmodel_load.
+At run time `choose` plans one graph: the installed model's pick, or
+exhaustive tuning of that graph when no matching model is installed.
 """
 from __future__ import annotations
 
@@ -298,6 +300,32 @@ def predict(model, X):
     apsp.apsp_costmodel_predict(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev), ch)
     torch.cuda.synchronize()
     return ch.cpu().numpy()
+
+
+def choose(Wd, exhaustive: bool = False, budget_s: float = 0.3):
+    """The plan for one graph already in device memory (square int32 or
+    float32 tensor): the installed cost model's pick (apsp_plan on the
+    graph's features) unless no model matching the candidate table is
+    installed or `exhaustive` is set; then exhaustive tuning, the model's
+    fallback: every candidate the dtype can run is timed on copies of the
+    graph and the fastest is kept.  Returns (opts, candidate index,
+    "model" or "exhaustive", {index: median seconds} or None)."""
+    import torch
+    from . import apsp
+    dtype = "float32" if Wd.dtype == torch.float32 else "int32"
+    f = features(Wd.cpu().numpy())
+    if not exhaustive:
+        o, ch = apsp.apsp_plan(Wd.shape[0], 10.0 ** f[1], 1, bool(f[3]), dtype=dtype)
+        if ch >= 0:
+            return o, ch, "model", None
+    times = {}
+    for i in range(apsp.apsp_candidate_count()):
+        o = apsp.apsp_candidate(i)
+        if dtype == "float32" and o.flags & apsp.FLAG_PACKED16:
+            continue
+        times[i] = time_candidate(torch, apsp, Wd, o, budget_s=budget_s)[0]
+    best = min(times, key=times.get)
+    return apsp.apsp_candidate(best), best, "exhaustive", times
 
 
 def size_rule(n, cands):

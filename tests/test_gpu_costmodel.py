@@ -224,3 +224,35 @@ def test_costmodel_file_round_trip(native, dev, tmp_path):
     assert e.value.status == native.APSP_E_ARG
     np.testing.assert_array_equal(native.apsp_costmodel_get_params(K), p0)
 
+
+
+def test_choose_model_pick_and_exhaustive_fallback(native, dev):
+    """autotune.choose: with a matching model installed it returns the
+    model's pick; without one (or when asked) it tunes exhaustively, returns
+    the fastest timed candidate, and that plan solves the graph exactly."""
+    import json
+    import os
+    from paper_2310_03983_amd import autotune
+    rng = np.random.default_rng(2024)
+    n = 300
+    W = np.where(rng.random((n, n)) < 0.02, rng.integers(1, 100, (n, n)), 1 << 30).astype(np.int32)
+    np.fill_diagonal(W, 0)
+    Wd = torch.from_numpy(W).to(dev)
+    ref = oracle.fw_i32(W, threads=8)
+    model = json.load(open(os.path.join(os.path.dirname(autotune.__file__), "data", "costmodel_mlp.json")))
+    autotune.install(model)
+    f = autotune.features(W)
+    o, ch, src, times = autotune.choose(Wd)
+    assert src == "model" and times is None
+    assert ch == native.apsp_plan(n, 10.0 ** f[1], 1, bool(f[3]))[1]
+    native.apsp_costmodel_init(3, 1)          # a model that does not match the candidate table
+    o, ch, src, times = autotune.choose(Wd, budget_s=0.05)
+    assert src == "exhaustive" and ch == min(times, key=times.get)
+    assert set(times) == set(range(native.apsp_candidate_count()))
+    D = Wd.clone()
+    native.apsp_solve(D, opts=o)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(D.cpu().numpy(), ref)
+    # fp32 graphs never get a capped 16-bit candidate
+    _, _, _, tf = autotune.choose(Wd.float(), exhaustive=True, budget_s=0.05)
+    assert all(not (native.apsp_candidate(i).flags & native.FLAG_PACKED16) for i in tf)
