@@ -308,6 +308,8 @@ def main():
     for s in range(args.warmup):
         solve(copies[s], cutover=args.cutover)
     torch.cuda.synchronize()
+    fold_kind = "packed16" if args.packed16 else "int32"
+    fold_before = apsp.apsp_measure_fold_rate(fold_kind)
     apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_128])
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -335,8 +337,11 @@ def main():
     k64 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_64)
     apsp.apsp_profile_enable(False)
 
-    # the fold's issue rate on this device now (spin kernel), beside the nominal peak
-    fold_rate = apsp.apsp_measure_fold_rate("packed16" if args.packed16 else "int32")
+    # the fold's issue rate on this device (spin kernel) before and after the
+    # timed steps; the higher one is the ceiling (a pure-VALU spin draws more
+    # power than the product, so its clock can sit below the product's)
+    fold_after = apsp.apsp_measure_fold_rate(fold_kind)
+    fold_rate = max(fold_before, fold_after, key=lambda r: r["terms_per_s"])
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = n ** 3 / (ms_per_step / 1e3)
@@ -386,7 +391,11 @@ def main():
         },
         "measured_ceiling": {
             "what": "spin kernel repeating the fold's own instructions on registers over the whole device "
-                    "(apsp_measure_fold_rate), run after the timed steps",
+                    "(apsp_measure_fold_rate), run before and after the timed steps; the higher rate is used. "
+                    "A pure-VALU spin draws more power than the product kernel, so its clock can be lower "
+                    "and frac can approach or pass 1",
+            "terms_per_s_before": fold_before["terms_per_s"],
+            "terms_per_s_after": fold_after["terms_per_s"],
             "terms_per_s": fold_rate["terms_per_s"],
             "lane_instr_per_s": fold_rate["lane_instr_per_s"],
             # equals the clock in GHz when the fold issues one lane-instruction per lane and cycle
