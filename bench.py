@@ -119,8 +119,10 @@ def bench_packed16(torch, apsp, Wd, n, cutover):
 
 def bench_small(torch, apsp, gg, dev):
     """The smaller single-graph configurations: n = 256 (blocked FW, one
-    closure-sized graph), n = 4096 by blocked FW and by R-Kleene, and the
-    last-hop predecessor product at n = 4096 (a dense argmin over n^3 terms)."""
+    closure-sized graph), n = 4096 by blocked FW and by R-Kleene, whole-graph
+    squaring at both sizes, blocked FW with and without INF-slice skipping on
+    a very sparse n = 8192 graph, and the last-hop predecessors at n = 4096
+    (dense argmin over n^3 terms, sparse form over n * m)."""
     out = {}
 
     def per_solve(fn, W, reps):
@@ -142,6 +144,20 @@ def bench_small(torch, apsp, gg, dev):
         t = per_solve(lambda d: apsp.apsp_fw(d, **kw), Wsp, 5)
         out[label] = {"ms_per_solve": t * 1e3, "updates_per_s": 8192 ** 3 / t}
     del Wsp
+    # whole-graph squaring to a fixpoint (Sec. 3.2, the paper's FW-GPU): every
+    # pass is one n x n x n product, the last one changes nothing
+    for label, W, reps, kw in (("n256_square_i32", W256, 50, {}), ("n4096_square_i32", W4k, 5, {}),
+                               ("n4096_square_i32_packed16", W4k, 5, {"packed16": True})):
+        nn = W.shape[0]
+        t = per_solve(lambda d: apsp.apsp_square(d, **kw), W, reps)
+        probe = W.clone()
+        apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_128, apsp.KERNEL_MINPLUS_64])
+        apsp.apsp_square(probe, **kw)
+        torch.cuda.synchronize()
+        passes = sum(apsp.apsp_profile_read(k)["launches"] for k in (apsp.KERNEL_MINPLUS_128, apsp.KERNEL_MINPLUS_64))
+        apsp.apsp_profile_enable(False)
+        out[label] = {"ms_per_solve": t * 1e3, "updates_per_s": nn ** 3 / t, "passes": passes,
+                      "terms_per_s": passes * nn ** 3 / t}
     D4k = W4k.clone()
     apsp.apsp_fw(D4k)
     m = int(torch.count_nonzero(W4k < (1 << 30)).item()) - 4096
