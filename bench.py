@@ -281,7 +281,14 @@ def cpu_baseline(W, sources_all, n, target_s):
         grow = max(2.0, min(8.0, target_s / max(t, 1e-3)))
         count = min(len(sources_all), int(count * grow) // threads * threads)
     t_full = t * n / count
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu_model)
+    except OSError:
+        pass
     return {"value": n ** 3 / t_full, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model,
             "sample": f"Dijkstra (binary heap, OpenMP over sources) from {count} of {n} seeded sources of the "
                       f"same graph in {t:.1f} s; full APSP extrapolated x{n / count:.1f} = {t_full:.0f} s; "
                       f"value = n^3 / extrapolated time"}
