@@ -32,6 +32,7 @@ struct apsp_ctx {
     hipStream_t side = nullptr;     // second stream of the FW look-ahead
     hipEvent_t ev_a = nullptr;      // look-ahead: band r+1 current
     hipEvent_t ev_p = nullptr;      // look-ahead: pivot r+1 and panels done
+    hipEvent_t ev_b = nullptr;      // look-ahead: the previous round's remainder done
     // cached batched plan: queue order on the device and the captured launch
     uint64_t bkey = 0;
     int32_t bcount = 0;
@@ -313,11 +314,10 @@ apsp_status_t closure(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int
 // ---------------------------------------------------------------------------
 // phases 1 and 2 of round (k0, bk): close the pivot tile, then the row panel
 // R_KJ <- X* (min,+) R_KJ and the column panel C_IK <- C_IK (min,+) X*
-apsp_status_t fw_pivot_panels(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
-                              int64_t k0, int64_t bk, const Plan& pl, hipStream_t st)
+apsp_status_t fw_panels(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
+                        int64_t k0, int64_t bk, const Plan& pl, hipStream_t st)
 {
-    apsp_status_t rc = closure(ctx, dt, D, ld, off + k0, bk, pl.closure, st);
-    if (rc || bk == n) return rc;
+    if (bk == n) return APSP_OK;
     const int t_p2 = apsp::TILE_64;                 // panels are thin: small tiles
     const apsp::TileShape s2 = apsp::tile_shape(t_p2);
     apsp::GemmGroup g2{};
@@ -329,6 +329,30 @@ apsp_status_t fw_pivot_panels(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t
     g2.p[1].skip_m0 = (int32_t)(k0 / s2.mt);
     g2.p[1].skip_mc = (int32_t)((bk + s2.mt - 1) / s2.mt);
     return run_group(ctx, dt, g2, pl, t_p2, st);
+}
+
+apsp_status_t fw_pivot_panels(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
+                              int64_t k0, int64_t bk, const Plan& pl, hipStream_t st)
+{
+    apsp_status_t rc = closure(ctx, dt, D, ld, off + k0, bk, pl.closure, st);
+    if (rc) return rc;
+    return fw_panels(ctx, dt, D, ld, off, n, k0, bk, pl, st);
+}
+
+// Pivot block (k1, k1) of the next round, fused: round (k0, bk)'s update of
+// that block from its panel blocks C(k1, k0) and R(k0, k1), then its closure.
+apsp_status_t fw_pivot_fused(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t k0,
+                             int64_t bk, int64_t k1, int64_t bk1, hipStream_t st)
+{
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    const double terms = (double)bk1 * bk1 * (bk1 + bk), bytes = 8.0 * bk1 * bk1 + 8.0 * bk1 * bk;
+    return timed(ctx, APSP_KERNEL_CLOSURE, terms, bytes, st, [&]() -> apsp_status_t {
+        HIP_TRY(apsp::launch_pivot_fused(dt == APSP_F32 ? apsp::F32 : apsp::I32, elem(D, dt, off + k1, off + k1, ld),
+                                         ld, elem(D, dt, off + k1, off + k0, ld), elem(D, dt, off + k0, off + k1, ld),
+                                         (int32_t)bk1, (int32_t)bk, st),
+                "fused pivot launch");
+        return APSP_OK;
+    });
 }
 
 // Remainder update D_IJ <- min(D_IJ, C_IK (min,+) R_KJ) of round (k0, bk) for
@@ -366,8 +390,12 @@ apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
     const apsp::TileShape s3 = apsp::tile_shape(t_p3), s64 = apsp::tile_shape(apsp::TILE_64);
     const int64_t rounds = (n + b - 1) / b;
     const bool ahead = pl.lookahead && rounds >= 3 && ctx->side && ctx->ev_a && ctx->ev_p;
+    // with k-loop closures the next pivot is updated and closed by one fused
+    // launch on the second stream from the start of each round
+    const bool fused = ahead && pl.closure == APSP_CLOSURE_KLOOP && ctx->ev_b && b <= 128;
     apsp_status_t rc = fw_pivot_panels(ctx, dt, D, ld, off, n, 0, std::min(b, n), pl, st);
     if (rc) return rc;
+    if (fused) HIP_TRY(hipEventRecord(ctx->ev_b, st), "look-ahead event");
     for (int64_t r = 0; r < rounds; ++r) {
         const int64_t k0 = r * b, bk = std::min(b, n - k0);
         if (bk == n) break;
@@ -384,22 +412,31 @@ apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
             continue;
         }
         const int64_t k1 = k0 + b, bk1 = std::min(b, n - k1);
-        // (a) band r+1: its row (all columns outside band r) and its column
-        //     (rows outside bands r and r+1), thin products on 64-tiles
+        if (fused) {
+            // (o) second stream, once the previous round's remainder is in:
+            //     pivot r+1 updated from round r's panels, then closed
+            HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_b, 0), "look-ahead wait");
+            rc = fw_pivot_fused(ctx, dt, D, ld, off, k0, bk, k1, bk1, ctx->side);
+            if (rc) return rc;
+        }
+        // (a) band r+1: its row (all columns outside band r, and outside band
+        //     r+1 when the pivot is fused) and its column (rows outside bands
+        //     r and r+1), thin products on 64-tiles
         apsp::GemmGroup ga{};
         ga.count = 2;
         ga.p[0] = make_problem(dt, D, ld, off + k1, off + k0, off + k0, off, off + k1, off, bk1, n, bk);
         ga.p[0].skip_n0 = (int32_t)(k0 / s64.nt);
-        ga.p[0].skip_nc = (int32_t)(bk / s64.nt);
+        ga.p[0].skip_nc = (int32_t)(((fused ? bk + bk1 : bk) + s64.nt - 1) / s64.nt);
         ga.p[1] = make_problem(dt, D, ld, off, off + k0, off + k0, off + k1, off, off + k1, n, bk1, bk);
         ga.p[1].skip_m0 = (int32_t)(k0 / s64.mt);
         ga.p[1].skip_mc = (int32_t)((bk + bk1 + s64.mt - 1) / s64.mt);
         rc = run_group(ctx, dt, ga, pl, apsp::TILE_64, st);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(ctx->ev_a, st), "look-ahead event");
-        // (b) second stream: pivot r+1 and its panels
+        // (b) second stream: pivot r+1 (unless fused) and its panels
         HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_a, 0), "look-ahead wait");
-        rc = fw_pivot_panels(ctx, dt, D, ld, off, n, k1, bk1, pl, ctx->side);
+        rc = fused ? fw_panels(ctx, dt, D, ld, off, n, k1, bk1, pl, ctx->side)
+                   : fw_pivot_panels(ctx, dt, D, ld, off, n, k1, bk1, pl, ctx->side);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(ctx->ev_p, ctx->side), "look-ahead event");
         // (c) caller's stream: every tile outside bands r and r+1
@@ -410,6 +447,7 @@ apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
             rc = run_group(ctx, dt, gb, pl, t_p3, st);
             if (rc) return rc;
         }
+        if (fused) HIP_TRY(hipEventRecord(ctx->ev_b, st), "look-ahead event");
         HIP_TRY(hipStreamWaitEvent(st, ctx->ev_p, 0), "look-ahead join");
     }
     return APSP_OK;
@@ -625,10 +663,12 @@ apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
     }
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_p, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_p, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming) != hipSuccess) {
         if (c->side) hipStreamDestroy(c->side);
         if (c->ev_a) hipEventDestroy(c->ev_a);
         if (c->ev_p) hipEventDestroy(c->ev_p);
+        if (c->ev_b) hipEventDestroy(c->ev_b);
         hipStreamDestroy(c->capture);
         delete c;
         return fail(APSP_E_HIP, "look-ahead stream creation failed");
@@ -640,6 +680,7 @@ apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
         hipStreamDestroy(c->side);
         hipEventDestroy(c->ev_a);
         hipEventDestroy(c->ev_p);
+        hipEventDestroy(c->ev_b);
         delete c;
         return fail(APSP_E_NOMEM, "scratch allocation: %s", hipGetErrorString(e));
     }
@@ -667,6 +708,7 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     if (ctx->side) hipStreamDestroy(ctx->side);
     if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
     if (ctx->ev_p) hipEventDestroy(ctx->ev_p);
+    if (ctx->ev_b) hipEventDestroy(ctx->ev_b);
     if (ctx->pred_counts) hipFree(ctx->pred_counts);
     if (ctx->pred_offsets) hipFree(ctx->pred_offsets);
     if (ctx->pred_edges) hipFree(ctx->pred_edges);

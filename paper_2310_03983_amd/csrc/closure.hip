@@ -143,6 +143,30 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count)
         p[e] = v;
 }
 
+// Next pivot of a blocked Floyd-Warshall round, fused in one 512-lane
+// workgroup: the round's update of the pivot block from its two panel blocks,
+// X <- min(X, Cp (min,+) Rp) over bk reduction steps (Sec. 2, Eq. 1 with k
+// in the round's band), then the closure X <- X* (the next round's pivot
+// step).  X, Cp and Rp are disjoint blocks of one matrix with stride ld.
+template <class S>
+__global__ __launch_bounds__(dev::kCloseWideThreads) void k_pivot_fused(typename S::T* X, int64_t ld,
+                                                                        const typename S::T* __restrict__ Cp,
+                                                                        const typename S::T* __restrict__ Rp, int w,
+                                                                        int bk)
+{
+    using T = typename S::T;
+    using P = typename S::P;
+    constexpr int KT = 16;
+    constexpr int kTileBytes = 2 * 2 * (KT / 2) * (kMaxS + 2) * (int)sizeof(P);
+    constexpr int kBytes = kTileBytes > dev::kCloseLdsWords * 4 ? kTileBytes : dev::kCloseLdsWords * 4;
+    __shared__ __attribute__((aligned(16))) char smem[kBytes];
+    auto As = reinterpret_cast<P (*)[KT / 2][kMaxS + 2]>(smem);
+    auto Bs = reinterpret_cast<P (*)[KT / 2][kMaxS + 2]>(smem + kTileBytes / 2);
+    dev::mp_tile<S, kMaxS, kMaxS, KT, 8, 4, true>(Cp, ld, Rp, ld, X, ld, w, w, 0, 0, 0, bk, false, nullptr, As, Bs);
+    __syncthreads();   // the block's stores are visible to the whole workgroup
+    dev::close_block_wide<S>(X, ld, w, reinterpret_cast<T*>(smem));
+}
+
 }  // namespace
 
 hipError_t launch_closure(DType dt, int kind, void* D, int64_t ld, int32_t s, hipStream_t st)
@@ -159,6 +183,19 @@ hipError_t launch_closure(DType dt, int kind, void* D, int64_t ld, int32_t s, hi
         else
             hipLaunchKernelGGL(k_closure_kloop<CF32>, dim3(1), dim3(dev::kCloseWideThreads), 0, st, (float*)D, ld, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_pivot_fused(DType dt, void* X, int64_t ld, const void* Cp, const void* Rp, int32_t w,
+                              int32_t bk, hipStream_t st)
+{
+    if (w <= 0) return hipSuccess;
+    if (dt == F32)
+        hipLaunchKernelGGL(k_pivot_fused<CF32>, dim3(1), dim3(dev::kCloseWideThreads), 0, st, (float*)X, ld,
+                           (const float*)Cp, (const float*)Rp, w, bk);
+    else
+        hipLaunchKernelGGL(k_pivot_fused<CI32>, dim3(1), dim3(dev::kCloseWideThreads), 0, st, (uint32_t*)X, ld,
+                           (const uint32_t*)Cp, (const uint32_t*)Rp, w, bk);
     return hipGetLastError();
 }
 

@@ -59,6 +59,11 @@ hipError_t launch_minplus(DType dt, int tile, const GemmGroup& g, bool skip, hip
 // Closure of an s x s diagonal block (s <= 128) held at D (leading dim ld).
 // kind: 1 = Eq. 1 k-loop, 2 = squaring to a fixpoint.
 hipError_t launch_closure(DType dt, int kind, void* D, int64_t ld, int32_t s, hipStream_t st);
+// Blocked FW pivot step fused: X <- min(X, Cp (min,+) Rp) over bk steps, then
+// X <- X* (k-loop closure), one workgroup; w <= 128, bk <= 128; int32 data
+// for I32 and I32P16.
+hipError_t launch_pivot_fused(DType dt, void* X, int64_t ld, const void* Cp, const void* Rp, int32_t w,
+                              int32_t bk, hipStream_t st);
 
 // Counts contract violations into *d_count (uint64, pre-zeroed by the kernel
 // launcher on the same stream).
