@@ -351,11 +351,13 @@ def main():
                                                       ("minplus_64", apsp.KERNEL_MINPLUS_64),
                                                       ("closure", apsp.KERNEL_CLOSURE))}
     apsp.apsp_profile_enable(False)
-    # panel phase: the 64x64 products of the FW windows (row and column
-    # panels, look-ahead band updates), recorded alone in one more solve
+    # panel phase: the 64x64 panel products of the FW windows, recorded alone
+    # in one more solve without look-ahead (with it they overlap the
+    # remainder on the second stream, and their event durations would
+    # include waiting for CUs)
     share_in.copy_(Wd)
     apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_64])
-    solve(share_in, cutover=args.cutover)
+    solve(share_in, cutover=args.cutover, lookahead=False)
     torch.cuda.synchronize()
     k64 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_64)
     apsp.apsp_profile_enable(False)
@@ -427,7 +429,8 @@ def main():
         },
         "panel_phase": {
             "kernel": "k_minplus<int32, 64x64 tile>" + (" (capped 16-bit)" if args.packed16 else ""),
-            "what": "FW panel products of the 4096 windows: row and column panels, look-ahead band updates (K = 128)",
+            "what": "FW panel products of the 4096 windows (row and column panels, K = 128), in a solve "
+                    "without look-ahead so that each launch runs alone",
             "launches_per_solve": k64["launches"],
             "ms_per_solve": k64["ms"],
             "bytes_per_launch": k64["bytes"] / max(k64["launches"], 1),
