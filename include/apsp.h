@@ -151,8 +151,10 @@ apsp_status_t apsp_closure(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  * D (n x n, ldd >= n) is overwritten with distances.  opts may be NULL.
  * By default round r+1's pivot closure and panel updates run on a second
  * stream of the context, overlapped with the rest of round r's remainder
- * update (APSP_FLAG_NO_LOOKAHEAD keeps everything on `stream`); the call
- * still returns with all work ordered before later work on `stream`.
+ * update; with k-loop closures round r's update of pivot block r+1 and its
+ * closure are one launch there (APSP_FLAG_NO_LOOKAHEAD keeps everything on
+ * `stream`); the call still returns with all work ordered before later
+ * work on `stream`.
  */
 apsp_status_t apsp_fw(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                       void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
