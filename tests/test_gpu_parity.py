@@ -297,3 +297,32 @@ def test_workload_n16384_f32_sampled(native, dev):
     native.apsp_rkleene(D)
     out = host(D[torch.from_numpy(src).to(dev)])
     assert_close_f32(out, ref)
+
+
+@pytest.mark.parametrize("block", [64, 128])
+def test_fw_schedules_agree(native, dev, block):
+    """Blocked FW with the fused next-pivot step (default look-ahead), with
+    squaring closures (look-ahead without the fused step) and without
+    look-ahead: each bit-identical to the oracle, including ragged last bands
+    and a leading dimension larger than n."""
+    rng = np.random.default_rng(910 + block)
+    for n in (3 * block + 1, 640, 1000, 1100):
+        W = rand_graph_i32(rng, n, min(0.5, 5.0 / n))
+        ref = oracle.fw_i32(W, threads=8)
+        for kw in ({}, {"closure": "square"}, {"lookahead": False}):
+            D = to_dev(W, dev)
+            native.apsp_fw(D, block=block, **kw)
+            np.testing.assert_array_equal(host(D), ref, err_msg=f"n={n} {kw}")
+        big = np.full((n, n + 7), 5, np.int32)
+        big[:, :n] = W
+        Dd = to_dev(big, dev)
+        native.apsp_fw(Dd[:, :n], block=block)
+        out = host(Dd)
+        np.testing.assert_array_equal(out[:, :n], ref, err_msg=f"strided n={n}")
+        assert (out[:, n:] == 5).all()
+    F = rand_graph_f32(rng, 900, 0.01)
+    ref64 = oracle.fw_f64(F.astype(np.float64), threads=8)
+    for kw in ({}, {"closure": "square"}):
+        D = to_dev(F, dev)
+        native.apsp_fw(D, block=block, **kw)
+        assert_close_f32(host(D), ref64)
