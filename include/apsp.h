@@ -20,22 +20,27 @@
  *
  * Memory and streams: every matrix, offset and size array passed to a compute
  * call is device memory owned by the caller; the library keeps no pointer
- * past the call.  `stream` is a hipStream_t (NULL = the legacy default
- * stream).  Compute calls only enqueue work and return; a device fault is
- * reported by the caller's next synchronisation.  Value preconditions
- * (diagonal 0, range) are not checked by compute calls; apsp_validate checks
- * them.
+ * past the call, except the workspace the caller registers with
+ * apsp_set_workspace (kept until replaced or the context is destroyed).  No
+ * compute call allocates or frees device memory: the only device memory a
+ * call uses beyond its arguments is that workspace and the context's 4 KB
+ * scratch (allocated by apsp_create).  `stream` is a hipStream_t (NULL = the
+ * legacy default stream).  Compute calls only enqueue work and return unless
+ * their comment says they synchronise; a device fault is reported by the
+ * caller's next synchronisation.  Value preconditions (diagonal 0, range)
+ * are not checked by compute calls; apsp_validate checks them.
  *
  * Errors: every call returns an apsp_status_t.  Argument errors are detected
  * before anything is enqueued.  apsp_last_error() returns a thread-local
  * message describing the last failure on the calling thread.
  *
- * Contexts: a context owns a second stream and two events (blocked FW's
+ * Contexts: a context owns a second stream and three events (blocked FW's
  * look-ahead and the batched schedule fork work onto it and join back onto
- * the caller's stream before returning), small device buffers and cached
- * batched plans.  It is not thread-safe: use it from one host thread at a
- * time, and do not let calls through one context run concurrently on
- * different streams (create one context per concurrent user).
+ * the caller's stream before returning), a 4 KB device scratch, the cost
+ * model's parameters and cached batched plans.  It is not thread-safe: use
+ * it from one host thread at a time, and do not let calls through one
+ * context run concurrently on different streams (create one context per
+ * concurrent user).
  */
 #ifndef APSP_H
 #define APSP_H
@@ -51,7 +56,8 @@ typedef int32_t apsp_status_t;
 #define APSP_OK             0
 #define APSP_E_ARG         -1   /* null pointer, negative size, ld too small, bad dtype/option */
 #define APSP_E_INPUT       -2   /* apsp_validate found a precondition violation */
-#define APSP_E_NOMEM       -3   /* device allocation for library scratch failed */
+#define APSP_E_NOMEM       -3   /* workspace missing or too small (apsp_workspace_size), or
+                                   apsp_create could not allocate its scratch */
 #define APSP_E_HIP         -4   /* a HIP runtime call or kernel launch failed */
 #define APSP_E_UNSUPPORTED -5   /* option not available for this dtype/size */
 #define APSP_E_STATE       -6   /* context not usable (wrong device, destroyed) */
@@ -105,8 +111,8 @@ typedef struct apsp_opts {
 
 typedef struct apsp_ctx apsp_ctx_t;
 
-/* Creates a context bound to HIP device `device` and allocates its small
- * device scratch (counters, batched plan table).  *ctx receives the handle. */
+/* Creates a context bound to HIP device `device` and allocates its 4 KB
+ * device scratch (counters and flags).  *ctx receives the handle. */
 apsp_status_t apsp_create(apsp_ctx_t **ctx, int32_t device);
 
 /* Synchronises the device, frees the scratch and the handle.  NULL is a no-op. */
@@ -117,6 +123,40 @@ const char *apsp_last_error(void);
 
 /* Library version string. */
 const char *apsp_version(void);
+
+/*
+ * Workspace.  apsp_batched (its plan: queue order, work items, a pointer
+ * record) and the sparse form of apsp_predecessors_ex (edge counts, offsets,
+ * edge list) need device memory beyond their arguments; the caller provides
+ * it once with apsp_set_workspace and the library never allocates it.
+ * apsp_workspace_size returns the bytes an operation needs:
+ *   APSP_OP_SOLVE         apsp_fw / apsp_rkleene / apsp_square / apsp_solve /
+ *                         minplus_gemm / apsp_closure / apsp_validate: 0;
+ *   APSP_OP_BATCHED       n_or_total = the largest n of the batch, count = the
+ *                         number of graphs: an upper bound for any batch of
+ *                         that shape;
+ *   APSP_OP_PREDECESSORS  n_or_total = n: the sparse form for every graph the
+ *                         automatic choice takes sparse (up to n^2/4 edges);
+ *                         0 for n > 65535 (dense only).
+ * Returns 0 (and sets the last error) for an invalid context, dtype, op or
+ * negative size.
+ */
+#define APSP_OP_SOLVE        0
+#define APSP_OP_BATCHED      1
+#define APSP_OP_PREDECESSORS 2
+size_t apsp_workspace_size(apsp_ctx_t *ctx, int32_t op, apsp_dtype_t dtype, int64_t n_or_total, int32_t count);
+
+/*
+ * Registers `bytes` of caller-owned device memory at d_ptr (256-byte
+ * aligned; NULL with 0 clears it) as the context's workspace.  The library
+ * keeps the pointer until it is replaced or the context is destroyed; the
+ * caller keeps the memory alive that long and does not use it meanwhile.
+ * Replacing a workspace drops the cached batched plans (they point into it)
+ * after waiting for the device.  Every compute call that uses the workspace
+ * overwrites it, so calls through one context that use it must not overlap.
+ * Errors: APSP_E_ARG for a NULL pointer with bytes > 0 or a misaligned one.
+ */
+apsp_status_t apsp_set_workspace(apsp_ctx_t *ctx, void *d_ptr, size_t bytes);
 
 /*
  * Min-plus product, accumulating form (Sec. 3, Eq. 2):
@@ -223,24 +263,46 @@ apsp_status_t apsp_predecessors(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                                 int32_t *P, int64_t ldp, void *stream);
 
 /* Forms of the predecessor computation (all give the same P). */
-#define APSP_PRED_AUTO   0  /* sparse when W has at most n^2/4 edges and n <= 65535, else dense */
+#define APSP_PRED_AUTO   0  /* sparse when W has at most n^2/4 edges, they fit the workspace and
+                               n <= 65535, else dense */
 #define APSP_PRED_DENSE  1  /* one argmin product over every v: n^3 terms (add, compare, two selects) */
 #define APSP_PRED_SPARSE 2  /* only the in-edges of j: n * m candidates; n <= 65535 */
 
 /*
  * apsp_predecessors with a chosen form.  Only v with W[v][j] < INF can make
  * D[i][v] (+) W[v][j] fall below INF, so the sparse form takes the argmin
- * over j's in-edges alone: it lists W's m edges (one pass over W, then one
- * more to write them; the count is read back, so the call synchronises
- * `stream`), keeps the context's edge list (8 bytes per edge) for the call,
- * and folds (value, v) keys with 64-bit LDS atomic minima, ties to the
- * smallest v.  APSP_PRED_AUTO and APSP_PRED_SPARSE synchronise `stream`;
- * APSP_PRED_DENSE only enqueues.  Errors: method outside 0..2 is
- * APSP_E_ARG; APSP_PRED_SPARSE with n > 65535 is APSP_E_UNSUPPORTED.
+ * over j's in-edges alone: on the device it counts W's edges per row and
+ * column range, scans the counts into an edge-list layout in the workspace,
+ * lists the m edges and folds (value, v) keys with 64-bit LDS atomic minima,
+ * ties to the smallest v.  Whether the sparse or the dense form writes P is
+ * decided on the device (both are enqueued; the other returns at once):
+ * sparse when the edge list fits the workspace and, for APSP_PRED_AUTO,
+ * m <= n^2/4.  Nothing is read back, so every form only enqueues.  Without a
+ * workspace larger than its fixed part (flag, counts, offsets), AUTO runs
+ * the dense form and SPARSE returns APSP_E_NOMEM.  All forms give the same
+ * P.  Errors: method outside 0..2 is APSP_E_ARG; APSP_PRED_SPARSE with
+ * n > 65535 is APSP_E_UNSUPPORTED.
  */
 apsp_status_t apsp_predecessors_ex(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                                    const void *D, int64_t ldd, const void *W, int64_t ldw,
                                    int32_t *P, int64_t ldp, int32_t method, void *stream);
+
+/*
+ * Path reconstruction (Sec. 2: the shortest path is recovered by following
+ * the predecessor of the target back to the source).  For each of `count`
+ * queries q, follows P (n x n int32, ldp, as written by apsp_predecessors)
+ * back from d_dst[q] to d_src[q] and writes the path's vertices, source
+ * first, to d_paths[q * max_len ...]; d_len[q] receives the number of
+ * vertices: 1 when source == target, 0 when the target is unreachable
+ * (P[s][t] < 0), -1 when a vertex index is out of range, the chain leaves
+ * [0, n) or the path has more than min(max_len, n) vertices.  All arrays are
+ * device memory (d_src, d_dst, d_len: count int32; d_paths: count * max_len
+ * int32); one lane per query, enqueued only.  Errors: APSP_E_ARG for
+ * count < 0, max_len < 1 or a NULL array.
+ */
+apsp_status_t apsp_path(apsp_ctx_t *ctx, int64_t n, const int32_t *P, int64_t ldp, int32_t count,
+                        const int32_t *d_src, const int32_t *d_dst, int32_t *d_paths, int32_t max_len,
+                        int32_t *d_len, void *stream);
 
 /*
  * Many independent graphs, solved together.  `data` holds `count` square
@@ -260,10 +322,12 @@ apsp_status_t apsp_predecessors_ex(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t 
  * whole graphs, largest first, from an atomic queue (also graph-captured).
  * APSP_FLAG_BATCH_NO_GRAPH launches directly; APSP_FLAG_BATCH_PER_GRAPH
  * issues one launch per graph (a baseline).  n <= 1024 per graph
- * (APSP_E_UNSUPPORTED beyond: use apsp_solve).  The context keeps the plan
- * in device memory it allocates when a new batch shape arrives (that call
- * synchronises `stream`); calls on one context must not overlap across
- * streams.
+ * (APSP_E_UNSUPPORTED beyond: use apsp_solve).  The plan lives in the
+ * workspace (apsp_workspace_size with APSP_OP_BATCHED); a workspace that is
+ * missing or too small is APSP_E_NOMEM, returned before anything is
+ * enqueued.  A call with a new batch shape, or after another call used the
+ * workspace, uploads the plan and synchronises `stream`; calls on one
+ * context must not overlap across streams.
  */
 apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
                            void *data, const int64_t *d_offsets, const int32_t *d_sizes,

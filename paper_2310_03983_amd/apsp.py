@@ -38,7 +38,9 @@ EXPORTS = [
     "apsp_costmodel_train", "apsp_costmodel_grad",
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
     "apsp_packed16_counts", "apsp_predecessors_ex", "apsp_measure_fold_rate",
+    "apsp_workspace_size", "apsp_set_workspace", "apsp_path",
 ]
+OP = {"solve": 0, "batched": 1, "predecessors": 2}
 FOLD = {"int32": 0, "float32": 1, "packed16": 2}
 PRED = {"auto": 0, "dense": 1, "sparse": 2}
 
@@ -87,6 +89,7 @@ def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, spli
 _lock = threading.Lock()
 _lib = None
 _ctxs: dict[int, ctypes.c_void_p] = {}
+_ws: dict[int, torch.Tensor] = {}     # workspace registered with each device's context
 
 
 def lib() -> ctypes.CDLL:
@@ -130,9 +133,13 @@ def lib() -> ctypes.CDLL:
             L.apsp_costmodel_forward.argtypes = [vp, vp, i32, vp, vp]
             L.apsp_costmodel_predict.argtypes = [vp, vp, i32, vp, vp]
             L.apsp_plan.argtypes = [vp, i32, i64, ctypes.c_double, i32, i32, P(Opts), P(i32)]
+            L.apsp_workspace_size.argtypes = [vp, i32, i32, i64, i32]
+            L.apsp_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+            L.apsp_path.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, i32, vp, vp]
             for name in EXPORTS:
-                if name not in ("apsp_last_error", "apsp_version"):
+                if name not in ("apsp_last_error", "apsp_version", "apsp_workspace_size"):
                     getattr(L, name).restype = i32
+            L.apsp_workspace_size.restype = ctypes.c_size_t
             _lib = L
     return _lib
 
@@ -158,6 +165,37 @@ def context(device: int | None = None) -> ctypes.c_void_p:
         with _lock:
             _ctxs[device] = c
     return c
+
+
+def apsp_workspace_size(op: str, n_or_total: int, count: int = 0, dtype: str = "int32",
+                        device: int | None = None) -> int:
+    """Bytes of workspace `op` ("solve", "batched", "predecessors") needs."""
+    dt = {"int32": APSP_I32, "float32": APSP_F32}[dtype]
+    return int(lib().apsp_workspace_size(context(device), OP[op], dt, int(n_or_total), int(count)))
+
+
+def apsp_set_workspace(buf: torch.Tensor | None, device: int | None = None):
+    """Registers a device tensor (any dtype, contiguous) as the context's
+    workspace, or clears it with None.  The binding keeps a reference."""
+    if device is None:
+        device = buf.device.index if buf is not None else torch.cuda.current_device()
+    if buf is None:
+        _check(lib().apsp_set_workspace(context(device), None, 0))
+        _ws.pop(device, None)
+        return
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise TypeError("workspace must be a contiguous device tensor")
+    _check(lib().apsp_set_workspace(context(device), buf.data_ptr(), buf.numel() * buf.element_size()))
+    _ws[device] = buf
+
+
+def _ensure_workspace(op: str, dt: int, n_or_total: int, count: int, device: int):
+    """Allocates (through torch) and registers a workspace large enough for
+    `op` when the registered one is smaller."""
+    need = int(lib().apsp_workspace_size(context(device), OP[op], dt, int(n_or_total), int(count)))
+    cur = _ws.get(device)
+    if need and (cur is None or cur.numel() < need):
+        apsp_set_workspace(torch.empty(need, dtype=torch.uint8, device=torch.device("cuda", device)), device)
 
 
 def _dtype(t: torch.Tensor) -> int:
@@ -260,28 +298,44 @@ def apsp_predecessors(D, W, P=None, stream=None, method="auto"):
     if P.dtype != torch.int32:
         raise TypeError("P must be int32")
     pp, ldp = _matrix(P, "P")
+    if method != "dense":
+        _ensure_workspace("predecessors", dt, n, 0, D.device.index)
     _check(lib().apsp_predecessors_ex(context(D.device.index), dt, n, pd, ldd, pw, ldw, pp, ldp, PRED[method],
                                       _stream(D, stream)))
     return P
 
 
-def reconstruct_path(P_row, i: int, j: int) -> list[int]:
-    """Vertices of the i -> j path encoded by row i of a predecessor matrix
-    (host array); [] when j is unreachable."""
-    if i == j:
-        return [i]
-    if P_row[j] < 0:
-        return []
-    path = [j]
-    v = j
-    for _ in range(len(P_row)):
-        v = int(P_row[v])
-        if v < 0:
-            raise ValueError("broken predecessor chain")
-        path.append(v)
-        if v == i:
-            return path[::-1]
-    raise ValueError("predecessor chain does not reach the source")
+def apsp_path(P: torch.Tensor, src, dst, max_len: int | None = None, stream=None) -> list[list[int]]:
+    """Vertices of the src[q] -> dst[q] paths encoded by the predecessor
+    matrix P (apsp_path; Sec. 2): one list per query, source first, [] when
+    the target is unreachable.  src and dst are ints or equal-length
+    sequences.  Raises ValueError for a broken chain."""
+    if P.dtype != torch.int32:
+        raise TypeError("P must be int32")
+    pp, ldp = _matrix(P, "P")
+    n = P.shape[0]
+    single = isinstance(src, int) and isinstance(dst, int)
+    s_ = [int(src)] if single else [int(x) for x in src]
+    d_ = [int(dst)] if single else [int(x) for x in dst]
+    if len(s_) != len(d_):
+        raise ValueError("src and dst differ in length")
+    count = len(s_)
+    L = int(max_len or max(n, 1))
+    dev = P.device
+    sd = torch.tensor(s_, dtype=torch.int32, device=dev)
+    dd = torch.tensor(d_, dtype=torch.int32, device=dev)
+    paths = torch.empty((max(count, 1), L), dtype=torch.int32, device=dev)
+    lens = torch.empty(max(count, 1), dtype=torch.int32, device=dev)
+    _check(lib().apsp_path(context(dev.index), n, pp, ldp, count, sd.data_ptr(), dd.data_ptr(), paths.data_ptr(), L,
+                           lens.data_ptr(), _stream(P, stream)))
+    lh = lens.cpu().tolist()
+    ph = paths.cpu()
+    out = []
+    for q in range(count):
+        if lh[q] < 0:
+            raise ValueError(f"broken predecessor chain for {s_[q]} -> {d_[q]}")
+        out.append(ph[q, :lh[q]].tolist())
+    return out[0] if single else out
 
 
 def apsp_validate(D, stream=None) -> int:
@@ -307,6 +361,8 @@ def apsp_batched(data: torch.Tensor, offsets: torch.Tensor, sizes: torch.Tensor,
     count = len(h_sizes)
     hs = (ctypes.c_int32 * max(count, 1))(*[int(x) for x in h_sizes])
     o = _opts(opts, kw)
+    if count:
+        _ensure_workspace("batched", dt, max(int(x) for x in h_sizes), count, data.device.index)
     _check(lib().apsp_batched(context(data.device.index), dt, count, data.data_ptr(), offsets.data_ptr(),
                               sizes.data_ptr(), hs, ctypes.byref(o), _stream(data, stream)))
     return data

@@ -24,10 +24,11 @@ struct ProfRec {
 struct apsp_ctx {
     int device = 0;
     int num_cus = 256;
-    void* d_scratch = nullptr;      // counters and flags
+    void* d_scratch = nullptr;      // counters and flags (allocated by apsp_create)
     size_t scratch_bytes = 0;
-    void* d_plan = nullptr;         // batched plan table (grown on demand)
-    size_t plan_bytes = 0;
+    char* ws = nullptr;             // caller's workspace (apsp_set_workspace)
+    size_t ws_bytes = 0;
+    int ws_owner = 0;               // what the workspace holds now (WS_*)
     hipStream_t capture = nullptr;  // private stream used only for graph capture
     hipStream_t side = nullptr;     // second stream of the FW look-ahead
     hipEvent_t ev_a = nullptr;      // look-ahead: band r+1 current
@@ -47,9 +48,7 @@ struct apsp_ctx {
     std::vector<int4> litems;
     struct Launch { int phase, offset, count; bool side; };   // side: on the second stream
     std::vector<Launch> llaunches;
-    int4* d_items = nullptr;
-    size_t items_bytes = 0;
-    apsp::BatchPtrs* d_bptrs = nullptr;
+    size_t bplan_bytes = 0;         // workspace bytes the cached plan occupies
     hipGraph_t lgraph = nullptr;
     hipGraphExec_t lexec = nullptr;
     // cost model
@@ -67,12 +66,6 @@ struct apsp_ctx {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
-    int32_t* pred_counts = nullptr; // sparse predecessors: edge counts, offsets, packed edges
-    size_t pred_counts_bytes = 0;
-    int64_t* pred_offsets = nullptr;
-    size_t pred_offsets_bytes = 0;
-    uint64_t* pred_edges = nullptr;
-    size_t pred_edges_bytes = 0;
     int64_t p16_runs = 0;           // solves run with APSP_FLAG_PACKED16
     int64_t p16_redone = 0;         // ... of which were redone in int32
     uint32_t magic = 0x41505350;    // "APSP"
@@ -613,27 +606,55 @@ apsp_status_t check_model(apsp_ctx_t* ctx)
     return APSP_OK;
 }
 
-// Grows a context-held device buffer (synchronising `st` before a free).
-template <class T>
-apsp_status_t grow(T*& p, size_t& have, size_t need, hipStream_t st, const char* what)
-{
-    if (need <= have && p) return APSP_OK;
-    HIP_TRY(hipStreamSynchronize(st), "workspace sync");
-    if (p) hipFree(p);
-    p = nullptr;
-    have = 0;
-    hipError_t e = hipMalloc(&p, std::max<size_t>(need, 256));
-    if (e != hipSuccess) return fail(APSP_E_NOMEM, "%s allocation: %s", what, hipGetErrorString(e));
-    have = std::max<size_t>(need, 256);
-    return APSP_OK;
-}
-
 // Automatic choice of the predecessor form: the sparse one does n * m
 // candidate updates (each an LDS atomic) against the dense kernel's n^3
 // argmin terms, so it is used while the edges are a small share of n^2.
 constexpr double kPredSparseMaxDensity = 0.25;
 constexpr int64_t kPredSparseMaxN = 65535;
 
+
+// ---------------------------------------------------------------------------
+// Caller workspace (apsp_set_workspace): the only device memory a compute
+// call uses beyond its arguments and the context's 4 KB scratch.
+// ---------------------------------------------------------------------------
+constexpr size_t kWsAlign = 256;
+enum { WS_NONE = 0, WS_BATCHED = 1, WS_PRED = 2 };
+
+size_t align_up(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+// Sparse predecessors: [use-sparse flag][edge counts][offsets + range
+// starts][edge list]; the edge list takes whatever room is left.
+struct PredLayout {
+    size_t counts, offsets, edges;   // byte offsets; edges = size of the fixed part
+};
+PredLayout pred_layout(int64_t n)
+{
+    const int64_t nr = apsp::pred_sparse_ranges((int32_t)n);
+    const size_t cells = (size_t)nr * (size_t)n;
+    PredLayout L;
+    L.counts = kWsAlign;
+    L.offsets = L.counts + align_up(cells * sizeof(int32_t));
+    L.edges = L.offsets + align_up((cells + (size_t)nr + 1) * sizeof(int64_t));
+    return L;
+}
+size_t pred_ws_bytes(int64_t n)
+{
+    // room for every edge the automatic choice would still take sparse
+    const double m = kPredSparseMaxDensity * (double)n * (double)n;
+    return pred_layout(n).edges + align_up((size_t)m * sizeof(uint64_t));
+}
+
+// Batched lock-step plan: [pointer record][queue order][work items].
+size_t batched_items_bound(int max_n)
+{
+    const int64_t B = apsp::batched_round_width();
+    const int64_t nb = (max_n + B - 1) / B;
+    return (size_t)(1 + nb * (2 * (nb - 1) + 1 + 4 * nb * nb));
+}
+size_t batched_ws_bytes(int32_t count, size_t items)
+{
+    return kWsAlign + align_up((size_t)count * sizeof(int32_t)) + align_up(std::max<size_t>(items, 1) * sizeof(int4));
+}
 }  // namespace
 
 extern "C" {
@@ -648,6 +669,14 @@ apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
     *out = nullptr;
     if (device < 0) return fail(APSP_E_ARG, "device = %d", device);
     if (fault_injected("create")) return fail(APSP_E_HIP, "injected create failure");
+    if (fault_injected("hostctx")) {
+        // host-side tests without a GPU: a context with no device resources,
+        // enough for the checks a call makes before its first HIP call
+        apsp_ctx_t* c = new apsp_ctx_t();
+        c->device = device;
+        *out = c;
+        return APSP_OK;
+    }
     int count = 0;
     HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
     if (device >= count) return fail(APSP_E_ARG, "device %d of %d", device, count);
@@ -695,25 +724,70 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
     if (ctx->d_scratch) hipFree(ctx->d_scratch);
-    if (ctx->d_plan) hipFree(ctx->d_plan);
     for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
     free_costmodel(ctx);
     if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
     if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
     if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
     if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
-    if (ctx->d_items) hipFree(ctx->d_items);
-    if (ctx->d_bptrs) hipFree(ctx->d_bptrs);
     if (ctx->capture) hipStreamDestroy(ctx->capture);
     if (ctx->side) hipStreamDestroy(ctx->side);
     if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
     if (ctx->ev_p) hipEventDestroy(ctx->ev_p);
     if (ctx->ev_b) hipEventDestroy(ctx->ev_b);
-    if (ctx->pred_counts) hipFree(ctx->pred_counts);
-    if (ctx->pred_offsets) hipFree(ctx->pred_offsets);
-    if (ctx->pred_edges) hipFree(ctx->pred_edges);
     ctx->magic = 0;
     delete ctx;
+    return APSP_OK;
+}
+
+size_t apsp_workspace_size(apsp_ctx_t* ctx, int32_t op, apsp_dtype_t dt, int64_t n_or_total, int32_t count)
+{
+    if (check_ctx(ctx) || check_dtype(dt)) return 0;
+    if (n_or_total < 0 || count < 0) {
+        fail(APSP_E_ARG, "negative size");
+        return 0;
+    }
+    switch (op) {
+    case APSP_OP_SOLVE: return 0;
+    case APSP_OP_BATCHED: {
+        const int64_t max_n = std::min<int64_t>(n_or_total, apsp::batched_max_n());
+        if (count == 0 || max_n <= 1) return batched_ws_bytes(count, 1);
+        return batched_ws_bytes(count, (size_t)count * batched_items_bound((int)max_n));
+    }
+    case APSP_OP_PREDECESSORS:
+        if (n_or_total <= 1 || n_or_total > kPredSparseMaxN) return 0;
+        return pred_ws_bytes(n_or_total);
+    default:
+        fail(APSP_E_ARG, "op = %d", op);
+        return 0;
+    }
+}
+
+apsp_status_t apsp_set_workspace(apsp_ctx_t* ctx, void* d_ptr, size_t bytes)
+{
+    apsp_status_t rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (bytes > 0 && !d_ptr) return fail(APSP_E_ARG, "workspace pointer is NULL");
+    if (d_ptr && (reinterpret_cast<uintptr_t>(d_ptr) % kWsAlign) != 0)
+        return fail(APSP_E_ARG, "workspace must be %zu-byte aligned", kWsAlign);
+    if (d_ptr == ctx->ws && bytes == ctx->ws_bytes) return APSP_OK;
+    // captured batched launches point into the old workspace: let any that
+    // are still running finish before they are destroyed
+    if (ctx->bexec || ctx->lexec) HIP_TRY(hipDeviceSynchronize(), "workspace change sync");
+    if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
+    if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+    if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
+    if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
+    ctx->bexec = nullptr;
+    ctx->bgraph = nullptr;
+    ctx->bnode = nullptr;
+    ctx->lexec = nullptr;
+    ctx->lgraph = nullptr;
+    ctx->bkey = 0;
+    ctx->bcount = 0;
+    ctx->ws = bytes ? static_cast<char*>(d_ptr) : nullptr;
+    ctx->ws_bytes = bytes;
+    ctx->ws_owner = WS_NONE;
     return APSP_OK;
 }
 
@@ -860,54 +934,47 @@ apsp_status_t apsp_predecessors_ex(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, 
     if ((rc = check_ctx(ctx))) return rc;
     if (n == 0) return APSP_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // the sparse form needs the workspace's fixed part (flag, counts, offsets)
+    const PredLayout L = pred_layout(n);
+    const bool sparse_possible = method != APSP_PRED_DENSE && n <= kPredSparseMaxN;
+    const bool have_ws = ctx->ws && ctx->ws_bytes > L.edges;
+    if (method == APSP_PRED_SPARSE && !have_ws)
+        return fail(APSP_E_NOMEM, "sparse predecessors need a workspace of more than %zu bytes (apsp_workspace_size)",
+                    L.edges);
     if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
-    auto dense = [&]() -> apsp_status_t {
+    auto dense = [&](const uint32_t* skip_if_set) -> apsp_status_t {
         const double terms = (double)n * n * n;
         return timed(ctx, APSP_KERNEL_OTHER, terms, 12.0 * n * n, st, [&]() -> apsp_status_t {
-            HIP_TRY(apsp::launch_predecessors((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, st),
+            HIP_TRY(apsp::launch_predecessors((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, skip_if_set, st),
                     "predecessor launch");
             return APSP_OK;
         });
     };
-    if (method == APSP_PRED_DENSE || n > kPredSparseMaxN) return dense();
-    // count the edges per (row, column range), then choose and lay them out
-    const int nr = apsp::pred_sparse_ranges((int32_t)n);
-    const size_t cells = (size_t)nr * (size_t)n;
-    if ((rc = grow(ctx->pred_counts, ctx->pred_counts_bytes, cells * sizeof(int32_t), st, "edge counts")))
-        return rc;
-    HIP_TRY(apsp::launch_edge_count((apsp::DType)dt, W, ldw, (int32_t)n, ctx->pred_counts, st), "edge count launch");
-    std::vector<int32_t> counts(cells);
-    HIP_TRY(hipMemcpyAsync(counts.data(), ctx->pred_counts, cells * sizeof(int32_t), hipMemcpyDeviceToHost, st),
-            "edge count copy");
-    HIP_TRY(hipStreamSynchronize(st), "edge count sync");
-    std::vector<int64_t> offs(cells + nr + 1);   // offsets[r * n + v], then range_start[0..nr]
-    int64_t m = 0;
-    for (int r = 0; r < nr; ++r) {
-        offs[cells + r] = m;
-        for (int64_t v = 0; v < n; ++v) {
-            offs[(size_t)r * n + v] = m;
-            m += counts[(size_t)r * n + v];
-        }
-    }
-    offs[cells + nr] = m;
-    if (method == APSP_PRED_AUTO && (double)m > kPredSparseMaxDensity * (double)n * (double)n) return dense();
-    if ((rc = grow(ctx->pred_offsets, ctx->pred_offsets_bytes, offs.size() * sizeof(int64_t), st, "edge offsets")) ||
-        (rc = grow(ctx->pred_edges, ctx->pred_edges_bytes, (size_t)m * sizeof(uint64_t), st, "edge list")))
-        return rc;
-    HIP_TRY(hipMemcpyAsync(ctx->pred_offsets, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                           st),
-            "edge offset upload");
-    const double terms = (double)n * (double)m;
-    rc = timed(ctx, APSP_KERNEL_OTHER, terms, 8.0 * (double)m + 8.0 * n * n, st, [&]() -> apsp_status_t {
-        HIP_TRY(apsp::launch_pred_sparse((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, ctx->pred_offsets,
-                                         ctx->pred_offsets + cells, ctx->pred_edges, st),
+    if (!sparse_possible || !have_ws) return dense(nullptr);
+    // On the device: count each row's edges per column range, scan the counts
+    // into the edge-list layout and decide -- sparse when the list fits the
+    // workspace (and, for the automatic choice, m <= n^2/4), else dense.
+    // Both forms are enqueued; the one not chosen returns at once, so nothing
+    // is read back and the call only enqueues.
+    uint32_t* flag = reinterpret_cast<uint32_t*>(ctx->ws);
+    int32_t* counts = reinterpret_cast<int32_t*>(ctx->ws + L.counts);
+    int64_t* offs = reinterpret_cast<int64_t*>(ctx->ws + L.offsets);
+    uint64_t* edges = reinterpret_cast<uint64_t*>(ctx->ws + L.edges);
+    const int64_t cells = (int64_t)apsp::pred_sparse_ranges((int32_t)n) * n;
+    const int64_t edge_cap = (int64_t)((ctx->ws_bytes - L.edges) / sizeof(uint64_t));
+    const int64_t dense_limit = method == APSP_PRED_AUTO ? (int64_t)(kPredSparseMaxDensity * (double)n * (double)n)
+                                                         : INT64_MAX;
+    ctx->ws_owner = WS_PRED;
+    apsp_status_t rc2 = timed(ctx, APSP_KERNEL_OTHER, 0.0, 8.0 * n * n, st, [&]() -> apsp_status_t {
+        HIP_TRY(apsp::launch_edge_count((apsp::DType)dt, W, ldw, (int32_t)n, counts, st), "edge count launch");
+        HIP_TRY(apsp::launch_edge_scan(counts, (int32_t)n, offs, edge_cap, dense_limit, flag, st), "edge scan launch");
+        HIP_TRY(apsp::launch_pred_sparse((apsp::DType)dt, D, ldd, W, ldw, P, ldp, (int32_t)n, offs, offs + cells, edges,
+                                         flag, st),
                 "sparse predecessor launch");
         return APSP_OK;
     });
-    if (rc) return rc;
-    // the host copy of the offsets must outlive the upload
-    HIP_TRY(hipStreamSynchronize(st), "edge offset sync");
-    return APSP_OK;
+    if (rc2) return rc2;
+    return dense(flag);
 }
 
 apsp_status_t apsp_predecessors(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
@@ -916,6 +983,25 @@ apsp_status_t apsp_predecessors(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, con
     return apsp_predecessors_ex(ctx, dt, n, D, ldd, W, ldw, P, ldp, APSP_PRED_AUTO, stream);
 }
 
+
+apsp_status_t apsp_path(apsp_ctx_t* ctx, int64_t n, const int32_t* P, int64_t ldp, int32_t count,
+                        const int32_t* d_src, const int32_t* d_dst, int32_t* d_paths, int32_t max_len,
+                        int32_t* d_len, void* stream)
+{
+    apsp_status_t rc;
+    if ((rc = check_square(n, P, ldp))) return rc;
+    if (n > INT32_MAX) return fail(APSP_E_ARG, "n too large");
+    if (count < 0) return fail(APSP_E_ARG, "count = %d is negative", count);
+    if (max_len < 1) return fail(APSP_E_ARG, "max_len = %d (>= 1)", max_len);
+    if (count > 0 && (!d_src || !d_dst || !d_paths || !d_len)) return fail(APSP_E_ARG, "NULL query pointer");
+    if ((rc = check_ctx(ctx))) return rc;
+    if (count == 0) return APSP_OK;
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    HIP_TRY(apsp::launch_paths(P, ldp, (int32_t)n, count, d_src, d_dst, d_paths, max_len, d_len,
+                               static_cast<hipStream_t>(stream)),
+            "path launch");
+    return APSP_OK;
+}
 
 apsp_status_t apsp_validate(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd,
                             void* stream, int64_t* h_violations)
@@ -964,25 +1050,17 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
     uint64_t key = 1469598103934665603ull ^ (uint64_t)dt;
     for (int32_t g = 0; g < count; ++g) key = (key ^ (uint64_t)(uint32_t)h_sizes[g]) * 1099511628211ull;
     key ^= (uint64_t)count << 40;
-    if (key != ctx->bkey || count != ctx->bcount || dt != ctx->bdtype) {
-        std::vector<int32_t> order(count);
+    const bool rebuild = key != ctx->bkey || count != ctx->bcount || dt != ctx->bdtype;
+    std::vector<int32_t> order;
+    std::vector<int4> items;
+    std::vector<apsp_ctx::Launch> launches;
+    if (rebuild) {
+        order.resize(count);
         for (int32_t g = 0; g < count; ++g) order[g] = g;
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t a, int32_t b) { return h_sizes[a] > h_sizes[b]; });
-        const size_t need = (size_t)count * sizeof(int32_t);
-        if (need > ctx->plan_bytes) {
-            HIP_TRY(hipStreamSynchronize(st), "plan sync");
-            if (ctx->d_plan) hipFree(ctx->d_plan);
-            ctx->d_plan = nullptr;
-            ctx->plan_bytes = 0;
-            hipError_t e = hipMalloc(&ctx->d_plan, need);
-            if (e != hipSuccess) return fail(APSP_E_NOMEM, "plan allocation: %s", hipGetErrorString(e));
-            ctx->plan_bytes = need;
-        }
         // lock-step work items, graphs in largest-first order within each launch
         const int B = apsp::batched_round_width();
-        std::vector<int4> items;
-        std::vector<apsp_ctx::Launch> launches;
         int max_rounds = 0;
         for (int32_t g = 0; g < count; ++g) max_rounds = std::max(max_rounds, (h_sizes[g] + B - 1) / B);
         // Per round r: the pivot closures (round 0 only), the panel tiles,
@@ -1027,26 +1105,18 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
                     }
             });
         }
-        const size_t ib = std::max<size_t>(items.size(), 1) * sizeof(int4);
-        if (ib > ctx->items_bytes || !ctx->d_bptrs) {
-            HIP_TRY(hipStreamSynchronize(st), "plan sync");
-            if (ctx->d_items) hipFree(ctx->d_items);
-            ctx->d_items = nullptr;
-            ctx->items_bytes = 0;
-            hipError_t e = hipMalloc(&ctx->d_items, ib);
-            if (e == hipSuccess && !ctx->d_bptrs) e = hipMalloc(&ctx->d_bptrs, sizeof(apsp::BatchPtrs));
-            if (e != hipSuccess) return fail(APSP_E_NOMEM, "batch plan allocation: %s", hipGetErrorString(e));
-            ctx->items_bytes = ib;
-        }
-        ctx->border = std::move(order);
-        ctx->litems = std::move(items);
-        ctx->llaunches = std::move(launches);
-        HIP_TRY(hipMemcpyAsync(ctx->d_plan, ctx->border.data(), need, hipMemcpyHostToDevice, st), "plan upload");
-        if (!ctx->litems.empty())
-            HIP_TRY(hipMemcpyAsync(ctx->d_items, ctx->litems.data(), ctx->litems.size() * sizeof(int4),
-                                   hipMemcpyHostToDevice, st),
-                    "plan upload");
-        HIP_TRY(hipStreamSynchronize(st), "plan upload sync");
+    }
+    // the plan lives in the caller's workspace: [pointer record][order][items]
+    const size_t need = batched_ws_bytes(count, rebuild ? items.size() : ctx->litems.size());
+    if (!ctx->ws || ctx->ws_bytes < need)
+        return fail(APSP_E_NOMEM, "apsp_batched needs a workspace of %zu bytes (have %zu; apsp_workspace_size)", need,
+                    ctx->ws_bytes);
+    auto* d_bptrs = reinterpret_cast<apsp::BatchPtrs*>(ctx->ws);
+    auto* d_order = reinterpret_cast<int32_t*>(ctx->ws + kWsAlign);
+    auto* d_items = reinterpret_cast<int4*>(ctx->ws + kWsAlign + align_up((size_t)count * sizeof(int32_t)));
+    if (rebuild) {
+        // a replay of the previous plan may still be running
+        if (ctx->bexec || ctx->lexec) HIP_TRY(hipStreamSynchronize(st), "plan change sync");
         if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
         if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
         if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
@@ -1056,15 +1126,34 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
         ctx->bnode = nullptr;
         ctx->lexec = nullptr;
         ctx->lgraph = nullptr;
+        ctx->border = std::move(order);
+        ctx->litems = std::move(items);
+        ctx->llaunches = std::move(launches);
         ctx->bkey = key;
         ctx->bcount = count;
         ctx->bdtype = dt;
+        ctx->ws_owner = WS_NONE;
+    }
+    if (ctx->ws_owner != WS_BATCHED) {
+        // (re)upload the plan; the host vectors stay alive in the context, and
+        // the stream is synchronised so that no later plan replaces them while
+        // the copy may still read them (new batch shapes only)
+        HIP_TRY(hipMemcpyAsync(d_order, ctx->border.data(), (size_t)count * sizeof(int32_t), hipMemcpyHostToDevice,
+                               st),
+                "plan upload");
+        if (!ctx->litems.empty())
+            HIP_TRY(hipMemcpyAsync(d_items, ctx->litems.data(), ctx->litems.size() * sizeof(int4),
+                                   hipMemcpyHostToDevice, st),
+                    "plan upload");
+        HIP_TRY(hipStreamSynchronize(st), "plan upload sync");
+        ctx->ws_owner = WS_BATCHED;
+        ctx->bplan_bytes = need;
     }
     apsp::BatchArgs a{};
     a.data = data;
     a.offsets = d_offsets;
     a.sizes = d_sizes;
-    a.order = static_cast<const int32_t*>(ctx->d_plan);
+    a.order = d_order;
     a.count = count;
     a.counter = static_cast<uint32_t*>(ctx->d_scratch) + 8;
     const apsp::DType kdt = (apsp::DType)dt;
@@ -1094,14 +1183,14 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
                     forked = true;
                 }
                 if (!L.side && forked && L.phase == 1 && (e = join()) != hipSuccess) return e;
-                e = apsp::launch_batch_phase(kdt, L.phase, ctx->d_bptrs, ctx->d_items + L.offset, L.count,
+                e = apsp::launch_batch_phase(kdt, L.phase, d_bptrs, d_items + L.offset, L.count,
                                              L.side ? ctx->side : s2);
                 if (e != hipSuccess) return e;
             }
             return forked ? join() : hipSuccess;
         };
         return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
-            HIP_TRY(apsp::launch_batch_ptrs(ctx->d_bptrs, data, d_offsets, d_sizes, st), "batch pointer update");
+            HIP_TRY(apsp::launch_batch_ptrs(d_bptrs, data, d_offsets, d_sizes, st), "batch pointer update");
             // a one-launch schedule (every graph n <= 128) runs faster as a
             // direct launch than as a graph replay
             if ((o->flags & APSP_FLAG_BATCH_NO_GRAPH) || ctx->llaunches.size() <= 1) {

@@ -89,52 +89,72 @@ __global__ __launch_bounds__(256) void k_closure_square(typename S::T* __restric
     }
 }
 
-template <class S>
-__global__ void k_validate(const typename S::T* __restrict__ D, int64_t n, int64_t ld,
-                           unsigned long long* __restrict__ count);
+// Row-wise counting pass over an n x n matrix (HBM-bound): workgroups take
+// whole rows, every lane reads 16-byte vectors (four elements; any 4-byte
+// aligned row start works), four vectors in flight per lane, and the
+// per-lane counts are summed across the wave and the workgroup before one
+// 64-bit atomic per workgroup.  Test::bad(v, diagonal) decides an element.
+struct ValidI32 {
+    using T = uint32_t;
+    // a negative int32 reads as > INF
+    static __device__ __forceinline__ bool bad(uint32_t v, bool diag) { return diag ? v != 0u : v > kInfI32; }
+};
+struct ValidF32 {
+    using T = float;
+    // NaN fails both tests
+    static __device__ __forceinline__ bool bad(float v, bool diag) { return diag ? !(v == 0.0f) : !(v >= 0.0f); }
+};
+struct AtLeast {
+    using T = uint32_t;
+    uint32_t thr;
+    __device__ __forceinline__ bool bad(uint32_t v, bool) const { return v >= thr; }
+};
 
-template <>
-__global__ void k_validate<CI32>(const uint32_t* __restrict__ D, int64_t n, int64_t ld,
-                                 unsigned long long* __restrict__ count)
+constexpr int kCountThreads = 256;
+
+template <class Test>
+__global__ __launch_bounds__(kCountThreads) void k_count_rows(const typename Test::T* __restrict__ D, int64_t n,
+                                                              int64_t ld, Test test,
+                                                              unsigned long long* __restrict__ count)
 {
-    unsigned long long bad = 0;
-    const int64_t total = n * n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / n, c = e - r * n;
-        const uint32_t v = D[r * ld + c];   // negative int32 reads as > INF
-        if (r == c ? v != 0u : v > kInfI32) ++bad;
+    using T = typename Test::T;
+    using V = dev::Pair2<dev::Pair2<T>>;   // four elements, one dwordx4 access
+    constexpr int kStep = 4 * kCountThreads;          // elements per vector round
+    uint32_t hits = 0;
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const T* row = D + r * ld;
+        int64_t c = (int64_t)threadIdx.x * 4;
+        for (; c + 3 * kStep + 3 < n; c += 4 * kStep) {
+            V v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = dev::ld_vec<V>(row + c + q * kStep);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t c0 = c + q * kStep;
+                hits += test.bad(v[q].x.x, c0 == r) + test.bad(v[q].x.y, c0 + 1 == r) +
+                        test.bad(v[q].y.x, c0 + 2 == r) + test.bad(v[q].y.y, c0 + 3 == r);
+            }
+        }
+        for (; c + 3 < n; c += kStep) {
+            const V v = dev::ld_vec<V>(row + c);
+            hits += test.bad(v.x.x, c == r) + test.bad(v.x.y, c + 1 == r) + test.bad(v.y.x, c + 2 == r) +
+                    test.bad(v.y.y, c + 3 == r);
+        }
+        for (; c < n; ++c) hits += test.bad(row[c], c == r);
     }
-    if (bad) atomicAdd(count, bad);
+    // wave sum, then workgroup sum through LDS
+    for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off);
+    __shared__ uint32_t part[kCountThreads / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = hits;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int w = 0; w < kCountThreads / 64; ++w) tot += part[w];
+        if (tot) atomicAdd(count, tot);
+    }
 }
 
-template <>
-__global__ void k_validate<CF32>(const float* __restrict__ D, int64_t n, int64_t ld,
-                                 unsigned long long* __restrict__ count)
-{
-    unsigned long long bad = 0;
-    const int64_t total = n * n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / n, c = e - r * n;
-        const float v = D[r * ld + c];
-        if (r == c ? !(v == 0.0f) : !(v >= 0.0f)) ++bad;   // NaN fails both tests
-    }
-    if (bad) atomicAdd(count, bad);
-}
-
-__global__ void k_count_ge(const uint32_t* __restrict__ D, int64_t n, int64_t ld, uint32_t thr,
-                           unsigned long long* __restrict__ count)
-{
-    unsigned long long hits = 0;
-    const int64_t total = n * n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / n, c = e - r * n;
-        if (D[r * ld + c] >= thr) ++hits;
-    }
-    if (hits) atomicAdd(count, hits);
-}
+int count_grid(int64_t n) { return (int)std::min<int64_t>(n, 4096); }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count)
 {
@@ -204,14 +224,12 @@ hipError_t launch_validate(DType dt, const void* D, int64_t n, int64_t ld,
 {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)d_count, 0u, (int64_t)2);
     if (n <= 0) return hipGetLastError();
-    const int64_t total = n * n;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 2048);
     if (dt == I32)
-        hipLaunchKernelGGL(k_validate<CI32>, dim3((unsigned)blocks), dim3(256), 0, st,
-                           (const uint32_t*)D, n, ld, d_count);
+        hipLaunchKernelGGL(k_count_rows<ValidI32>, dim3(count_grid(n)), dim3(kCountThreads), 0, st,
+                           (const uint32_t*)D, n, ld, ValidI32{}, d_count);
     else
-        hipLaunchKernelGGL(k_validate<CF32>, dim3((unsigned)blocks), dim3(256), 0, st,
-                           (const float*)D, n, ld, d_count);
+        hipLaunchKernelGGL(k_count_rows<ValidF32>, dim3(count_grid(n)), dim3(kCountThreads), 0, st,
+                           (const float*)D, n, ld, ValidF32{}, d_count);
     return hipGetLastError();
 }
 
@@ -219,9 +237,8 @@ hipError_t launch_count_ge(const uint32_t* D, int64_t n, int64_t ld, uint32_t th
                            unsigned long long* d_count, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    const int64_t total = n * n;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_count_ge, dim3((unsigned)blocks), dim3(256), 0, st, D, n, ld, thr, d_count);
+    hipLaunchKernelGGL(k_count_rows<AtLeast>, dim3(count_grid(n)), dim3(kCountThreads), 0, st, D, n, ld,
+                       AtLeast{thr}, d_count);
     return hipGetLastError();
 }
 

@@ -130,16 +130,24 @@ int batched_max_n();
 // Sparse last-hop predecessors: column ranges of 1024, edges packed as
 // v | (j - range start) << 16 | cost bits << 32, ordered by v within a range.
 // launch_edge_count fills counts[r * n + v] (edges of row v in range r);
-// launch_pred_sparse writes the edges at offsets[r * n + v] and then P, using
-// range_start[0..ranges] (edge index of each range's first edge).  n <= 65535.
+// launch_edge_scan turns them into offsets[r * n + v], range starts at
+// offsets[cells + r] (cells = ranges * n) and the total at
+// offsets[cells + ranges], and sets *use_sparse = (m <= edge_cap &&
+// m <= dense_limit); launch_pred_sparse (skipped when !*use_sparse) writes
+// the edges and then P.  n <= 65535.
 int pred_sparse_ranges(int32_t n);
 hipError_t launch_edge_count(DType dt, const void* W, int64_t ldw, int32_t n, int32_t* counts, hipStream_t st);
+hipError_t launch_edge_scan(const int32_t* counts, int32_t n, int64_t* offsets, int64_t edge_cap,
+                            int64_t dense_limit, uint32_t* use_sparse, hipStream_t st);
 hipError_t launch_pred_sparse(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
                               int64_t ldp, int32_t n, const int64_t* offsets, const int64_t* range_start,
-                              uint64_t* edges, hipStream_t st);
-
+                              uint64_t* edges, const uint32_t* use_sparse, hipStream_t st);
+// Walks P back from dst[q] to src[q] for count queries (see apsp_path).
+hipError_t launch_paths(const int32_t* P, int64_t ldp, int32_t n, int32_t count, const int32_t* src,
+                        const int32_t* dst, int32_t* paths, int32_t max_len, int32_t* len, hipStream_t st);
+// Dense argmin form; returns at once when skip_if_set is non-NULL and *skip_if_set != 0.
 hipError_t launch_predecessors(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
-                               int64_t ldp, int32_t n, hipStream_t st);
+                               int64_t ldp, int32_t n, const uint32_t* skip_if_set, hipStream_t st);
 
 // ---- cost-model MLP (mlp.hip)
 constexpr int kMlpIn = 4;

@@ -23,9 +23,12 @@ constexpr int MT = 64, NT = 64, KT = 32, TM = 4, TN = 4;
 template <class S>
 __global__ __launch_bounds__(256) void k_predecessors(const typename S::T* __restrict__ D, int64_t ldd,
                                                       const typename S::T* __restrict__ W, int64_t ldw,
-                                                      int32_t* __restrict__ P, int64_t ldp, int n)
+                                                      int32_t* __restrict__ P, int64_t ldp, int n,
+                                                      const uint32_t* __restrict__ skip_if_set)
 {
     using T = typename S::T;
+    // the sparse form already wrote P (decided on the device)
+    if (skip_if_set && *skip_if_set) return;
     __shared__ T As[KT][MT + 1];   // As[k][row] = D[m0 + row][k0 + k]
     __shared__ T Bs[KT][NT + 1];   // Bs[k][col] = W[k0 + k][n0 + col] (INF on the diagonal)
     const int tiles_n = (n + NT - 1) / NT;
@@ -131,9 +134,10 @@ __global__ __launch_bounds__(256) void k_edge_count(const typename S::T* __restr
 template <class S>
 __global__ __launch_bounds__(256) void k_edge_fill(const typename S::T* __restrict__ W, int64_t ldw, int n,
                                                    int nranges, const int64_t* __restrict__ offsets,
-                                                   uint64_t* __restrict__ edges)
+                                                   uint64_t* __restrict__ edges, const uint32_t* __restrict__ use_sparse)
 {
     using T = typename S::T;
+    if (!*use_sparse) return;
     __shared__ int32_t wave_tot[4];
     const int v = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -171,9 +175,11 @@ template <class S>
 __global__ __launch_bounds__(kSparseThreads) void k_pred_sparse(const typename S::T* __restrict__ D, int64_t ldd,
                                                                 int n, const int64_t* __restrict__ range_start,
                                                                 const uint64_t* __restrict__ edges,
-                                                                int32_t* __restrict__ P, int64_t ldp)
+                                                                int32_t* __restrict__ P, int64_t ldp,
+                                                                const uint32_t* __restrict__ use_sparse)
 {
     using T = typename S::T;
+    if (!*use_sparse) return;
     __shared__ unsigned long long best[kRows * kRange];
     const int i0 = blockIdx.x * kRows, r = blockIdx.y;
     const int rows = min(kRows, n - i0);
@@ -226,6 +232,97 @@ __global__ __launch_bounds__(kSparseThreads) void k_pred_sparse(const typename S
     }
 }
 
+
+// Edge-list layout on the device: exclusive prefix sums of the range-major
+// counts (cells = nranges * n) give offsets[r * n + v]; offsets[cells + r]
+// receives the first edge of range r and offsets[cells + nranges] the edge
+// total m.  One workgroup: each lane sums a contiguous run of counts, the
+// run totals are scanned in LDS, and each lane writes its run's offsets.
+// Finally *use_sparse = 1 when the edge list fits (m <= edge_cap) and the
+// sparse form is wanted (m <= dense_limit), else 0 (the dense kernel then
+// writes P).
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_edge_scan(const int32_t* __restrict__ counts, int64_t cells,
+                                                            int32_t n, int nranges, int64_t* __restrict__ offsets,
+                                                            int64_t edge_cap, int64_t dense_limit,
+                                                            uint32_t* __restrict__ use_sparse)
+{
+    __shared__ int64_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int64_t per = (cells + kScanThreads - 1) / kScanThreads;
+    const int64_t b = min(cells, (int64_t)t * per), e = min(cells, b + per);
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += counts[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {   // inclusive scan of the run totals
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t ? part[t - 1] : 0;
+    // range starts are the offsets at indices r * n
+    int64_t r = (b + n - 1) / n, boundary = r * n;
+    for (int64_t i = b; i < e; ++i) {
+        if (i == boundary) {
+            offsets[cells + r] = run;
+            ++r;
+            boundary += n;
+        }
+        offsets[i] = run;
+        run += counts[i];
+    }
+    if (t == kScanThreads - 1) {
+        const int64_t m = part[kScanThreads - 1];
+        offsets[cells + nranges] = m;
+        *use_sparse = (m <= edge_cap && m <= dense_limit) ? 1u : 0u;
+    }
+}
+
+// Path reconstruction (Sec. 2: the path is recovered by following the
+// predecessor of the target back to the source).  One lane per query: the
+// first walk counts the vertices, the second writes them source first.  A
+// predecessor outside [0, n), a chain longer than max_len vertices (or than
+// n) gives length -1; an unreachable target (P[s][t] < 0, s != t) gives 0.
+__global__ __launch_bounds__(256) void k_paths(const int32_t* __restrict__ P, int64_t ldp, int32_t n, int32_t count,
+                                               const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                               int32_t* __restrict__ paths, int32_t max_len,
+                                               int32_t* __restrict__ len)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const int32_t s = src[q], t = dst[q];
+    int32_t* out = paths + (int64_t)q * max_len;
+    if (s < 0 || s >= n || t < 0 || t >= n) {
+        len[q] = -1;
+        return;
+    }
+    const int32_t* row = P + (int64_t)s * ldp;
+    if (s != t && row[t] < 0) {
+        len[q] = 0;
+        return;
+    }
+    const int32_t limit = min(max_len, n);
+    int32_t L = 1, v = t;
+    while (v != s) {
+        const int32_t u = row[v];
+        if (u < 0 || u >= n || L >= limit) {
+            len[q] = -1;
+            return;
+        }
+        v = u;
+        ++L;
+    }
+    v = t;
+    for (int32_t i = L - 1; i >= 0; --i) {
+        out[i] = v;
+        if (i) v = row[v];
+    }
+    len[q] = L;
+}
+
 }  // namespace
 
 int pred_sparse_ranges(int32_t n) { return (n + kRange - 1) / kRange; }
@@ -242,37 +339,55 @@ hipError_t launch_edge_count(DType dt, const void* W, int64_t ldw, int32_t n, in
     return hipGetLastError();
 }
 
+hipError_t launch_edge_scan(const int32_t* counts, int32_t n, int64_t* offsets, int64_t edge_cap,
+                            int64_t dense_limit, uint32_t* use_sparse, hipStream_t st)
+{
+    const int nr = pred_sparse_ranges(n);
+    hipLaunchKernelGGL(k_edge_scan, dim3(1), dim3(kScanThreads), 0, st, counts, (int64_t)nr * n, n, nr, offsets,
+                       edge_cap, dense_limit, use_sparse);
+    return hipGetLastError();
+}
+
 hipError_t launch_pred_sparse(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
                               int64_t ldp, int32_t n, const int64_t* offsets, const int64_t* range_start,
-                              uint64_t* edges, hipStream_t st)
+                              uint64_t* edges, const uint32_t* use_sparse, hipStream_t st)
 {
     const int nr = pred_sparse_ranges(n);
     const dim3 grid((unsigned)((n + kRows - 1) / kRows), (unsigned)nr);
     if (dt == I32) {
         hipLaunchKernelGGL(k_edge_fill<dev::SemI32>, dim3(n), dim3(256), 0, st, (const uint32_t*)W, ldw, n, nr,
-                           offsets, edges);
+                           offsets, edges, use_sparse);
         hipLaunchKernelGGL(k_pred_sparse<dev::SemI32>, grid, dim3(kSparseThreads), 0, st, (const uint32_t*)D, ldd,
-                           n, range_start, edges, P, ldp);
+                           n, range_start, edges, P, ldp, use_sparse);
     } else {
         hipLaunchKernelGGL(k_edge_fill<dev::SemF32>, dim3(n), dim3(256), 0, st, (const float*)W, ldw, n, nr,
-                           offsets, edges);
+                           offsets, edges, use_sparse);
         hipLaunchKernelGGL(k_pred_sparse<dev::SemF32>, grid, dim3(kSparseThreads), 0, st, (const float*)D, ldd,
-                           n, range_start, edges, P, ldp);
+                           n, range_start, edges, P, ldp, use_sparse);
     }
     return hipGetLastError();
 }
 
+hipError_t launch_paths(const int32_t* P, int64_t ldp, int32_t n, int32_t count, const int32_t* src,
+                        const int32_t* dst, int32_t* paths, int32_t max_len, int32_t* len, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_paths, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, P, ldp, n, count, src, dst,
+                       paths, max_len, len);
+    return hipGetLastError();
+}
+
 hipError_t launch_predecessors(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
-                               int64_t ldp, int32_t n, hipStream_t st)
+                               int64_t ldp, int32_t n, const uint32_t* skip_if_set, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     const int64_t tiles = (int64_t)((n + MT - 1) / MT) * ((n + NT - 1) / NT);
     if (dt == I32)
         hipLaunchKernelGGL(k_predecessors<dev::SemI32>, dim3((unsigned)tiles), dim3(256), 0, st,
-                           (const uint32_t*)D, ldd, (const uint32_t*)W, ldw, P, ldp, n);
+                           (const uint32_t*)D, ldd, (const uint32_t*)W, ldw, P, ldp, n, skip_if_set);
     else
         hipLaunchKernelGGL(k_predecessors<dev::SemF32>, dim3((unsigned)tiles), dim3(256), 0, st,
-                           (const float*)D, ldd, (const float*)W, ldw, P, ldp, n);
+                           (const float*)D, ldd, (const float*)W, ldw, P, ldp, n, skip_if_set);
     return hipGetLastError();
 }
 

@@ -149,17 +149,6 @@ def test_predecessors_argument_errors(native):
     assert "context" in native.last_error()
 
 
-def test_reconstruct_path_host_logic(native):
-    import numpy as np
-    row = np.array([-1, 0, 1, 1, -1], dtype=np.int32)   # 0->1->2, 0->1->3, 4 unreachable
-    assert native.reconstruct_path(row, 0, 2) == [0, 1, 2]
-    assert native.reconstruct_path(row, 0, 3) == [0, 1, 3]
-    assert native.reconstruct_path(row, 0, 4) == []
-    assert native.reconstruct_path(row, 0, 0) == [0]
-    with pytest.raises(ValueError):
-        native.reconstruct_path(np.array([-1, 2, 1], dtype=np.int32), 0, 2)
-
-
 def test_packed16_option_is_checked_before_any_device_call(native):
     L = native.lib()
     fake = ctypes.c_void_p(0x1000)

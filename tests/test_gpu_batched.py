@@ -115,3 +115,58 @@ def test_batched_rejects_large_graph(native, dev):
     with pytest.raises(native.ApspError) as e:
         native.apsp_batched(flat, off_d, sz_d, hs)
     assert e.value.status == native.APSP_E_UNSUPPORTED
+
+
+def test_batched_workspace_contract(native, dev):
+    """apsp_batched keeps its plan in the caller's workspace: without one, or
+    with one smaller than apsp_workspace_size says, it returns APSP_E_NOMEM
+    before enqueuing anything (the data stays untouched); a workspace of the
+    reported size works, also after a predecessor call reused it and after
+    the workspace was replaced."""
+    import ctypes
+    rng = np.random.default_rng(940)
+    mats = [rand_graph(rng, n, 4.0 / n) for n in (300, 40, 512, 129, 64)]
+    refs = [oracle.fw_i32(W) for W in mats]
+    L = native.lib()
+    ctx = native.context(dev.index)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    saved = native._ws.get(dev.index)
+
+    def call():
+        flat, off_d, sz_d, hs, off = pack(mats, dev)
+        before = flat.clone()
+        h = (ctypes.c_int32 * len(hs))(*hs)
+        o = native.make_opts()
+        rc = L.apsp_batched(ctx, 0, len(hs), flat.data_ptr(), off_d.data_ptr(), sz_d.data_ptr(), h,
+                            ctypes.byref(o), st)
+        return rc, flat, before, off, hs
+
+    try:
+        need = native.apsp_workspace_size("batched", 512, len(mats))
+        assert need > 0
+        native.apsp_set_workspace(None, dev.index)
+        rc, flat, before, _, _ = call()
+        assert rc == native.APSP_E_NOMEM and "workspace" in native.last_error()
+        torch.cuda.synchronize()
+        assert torch.equal(flat, before)
+        native.apsp_set_workspace(torch.empty(1024, dtype=torch.uint8, device=dev), dev.index)
+        rc, flat, before, _, _ = call()
+        assert rc == native.APSP_E_NOMEM
+        torch.cuda.synchronize()
+        assert torch.equal(flat, before)
+        for _ in range(2):
+            native.apsp_set_workspace(torch.empty(need, dtype=torch.uint8, device=dev), dev.index)
+            rc, flat, _, off, hs = call()
+            assert rc == native.APSP_OK
+            for ref, got in zip(refs, unpack(flat, off, hs)):
+                np.testing.assert_array_equal(got, ref)
+            # another user of the workspace in between: the plan is uploaded again
+            W = mats[0]
+            Dd = torch.from_numpy(refs[0]).to(dev)
+            native.apsp_predecessors(Dd, torch.from_numpy(W).to(dev), method="sparse")
+            rc, flat, _, off, hs = call()
+            assert rc == native.APSP_OK
+            for ref, got in zip(refs, unpack(flat, off, hs)):
+                np.testing.assert_array_equal(got, ref)
+    finally:
+        native.apsp_set_workspace(saved, dev.index)

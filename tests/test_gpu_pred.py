@@ -40,8 +40,8 @@ def test_paths_from_gpu_solve(native, dev):
     Dh, Ph = D.cpu().numpy(), P.cpu().numpy()
     np.testing.assert_array_equal(Ph, oracle.predecessors_i32(oracle.fw_i32(W), W))
     for i in range(0, 256, 17):
-        for j in range(256):
-            path = native.reconstruct_path(Ph[i], i, j)
+        paths = native.apsp_path(P, [i] * 256, list(range(256)))
+        for j, path in enumerate(paths):
             if Dh[i, j] >= INF:
                 assert path == []
             else:
@@ -84,11 +84,12 @@ def test_predecessors_f32_valid(native, dev):
     Dh, Ph = D.cpu().numpy().astype(np.float64), P.cpu().numpy()
     ref = oracle.fw_f64(W.astype(np.float64))
     for i in range(n):
+        paths = native.apsp_path(P, [i] * n, list(range(n)))
         for j in range(n):
             if i == j or np.isinf(ref[i, j]):
                 assert Ph[i, j] == -1
                 continue
-            path = native.reconstruct_path(Ph[i], i, j)
+            path = paths[j]
             w = sum(float(W[a, b]) for a, b in zip(path, path[1:]))
             assert abs(w - ref[i, j]) <= 1e-5 * ref[i, j]
 
@@ -140,3 +141,78 @@ def test_predecessor_forms_agree_n4096(native, dev):
     Pd = native.apsp_predecessors(D, Wd, method="dense")
     torch.cuda.synchronize()
     assert torch.equal(Ps, Pd)
+
+
+def test_path_walks(native, dev):
+    """apsp_path on a hand-made predecessor matrix: rows 0 and 1 encode
+    0->1->2, 0->1->3 with 4 unreachable from 0; row 2 has a cycle 0 <- 1 <- 0
+    that never reaches 2 (a broken chain)."""
+    P = np.full((5, 5), -1, np.int32)
+    P[0] = [-1, 0, 1, 1, -1]
+    P[2] = [1, 0, -1, 2, 2]
+    Pd = torch.from_numpy(P).to(dev)
+    assert native.apsp_path(Pd, 0, 2) == [0, 1, 2]
+    assert native.apsp_path(Pd, 0, 3) == [0, 1, 3]
+    assert native.apsp_path(Pd, 0, 4) == []
+    assert native.apsp_path(Pd, 0, 0) == [0]
+    assert native.apsp_path(Pd, [0, 0, 0], [1, 3, 0]) == [[0, 1], [0, 1, 3], [0]]
+    with pytest.raises(ValueError):
+        native.apsp_path(Pd, 2, 0)          # 0 <- 1 <- 0 ... never reaches 2
+    with pytest.raises(ValueError):
+        native.apsp_path(Pd, 0, 3, max_len=2)   # the path has 3 vertices
+    with pytest.raises(ValueError):
+        native.apsp_path(Pd, 0, 7)          # target out of range
+    assert native.apsp_path(Pd, [], []) == []
+
+
+def test_sparse_form_workspace(native, dev):
+    """The sparse form lives in the caller's workspace: without one, AUTO runs
+    the dense form and SPARSE is APSP_E_NOMEM; with a workspace too small for
+    the edge list the device falls back to the dense form; the results never
+    change."""
+    import ctypes
+    rng = np.random.default_rng(1300)
+    n = 700
+    W = rand_graph(rng, n, 0.02, 1, 8)
+    D = oracle.fw_i32(W)
+    ref = oracle.predecessors_i32(D, W)
+    Dd, Wd = torch.from_numpy(D).to(dev), torch.from_numpy(W).to(dev)
+    L = native.lib()
+    ctx = native.context(dev.index)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call(method):
+        P = torch.full((n, n), 7, dtype=torch.int32, device=dev)
+        rc = L.apsp_predecessors_ex(ctx, 0, n, Dd.data_ptr(), n, Wd.data_ptr(), n, P.data_ptr(), n,
+                                    native.PRED[method], st)
+        torch.cuda.synchronize()
+        return rc, P.cpu().numpy()
+
+    saved = native._ws.get(dev.index)
+    try:
+        native.apsp_set_workspace(None, dev.index)
+        rc, P = call("auto")
+        assert rc == native.APSP_OK
+        np.testing.assert_array_equal(P, ref)
+        rc, _ = call("sparse")
+        assert rc == native.APSP_E_NOMEM and "workspace" in native.last_error()
+        full = native.apsp_workspace_size("predecessors", n)
+        m = int((W < INF).sum()) - n
+        # 16 KB: above the fixed part at n = 700 (flag 256 B, counts 3 KB,
+        # offsets 5.5 KB) but room for only ~900 of the ~9800 edges, so the
+        # device falls back to the dense form
+        small = torch.empty(16384, dtype=torch.uint8, device=dev)
+        native.apsp_set_workspace(small, dev.index)
+        for method in ("auto", "sparse"):
+            rc, P = call(method)
+            assert rc == native.APSP_OK
+            np.testing.assert_array_equal(P, ref, err_msg=method)
+        big = torch.empty(full, dtype=torch.uint8, device=dev)
+        native.apsp_set_workspace(big, dev.index)
+        for method in ("auto", "sparse", "dense"):
+            rc, P = call(method)
+            assert rc == native.APSP_OK
+            np.testing.assert_array_equal(P, ref, err_msg=method)
+        assert m > 2000
+    finally:
+        native.apsp_set_workspace(saved, dev.index)
