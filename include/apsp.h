@@ -334,6 +334,25 @@ apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
                            const int32_t *h_sizes, const apsp_opts_t *opts, void *stream);
 
 /*
+ * apsp_batched for callers that cannot allocate device memory or register a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same schedules and results as apsp_batched,
+ * with the plan held in a fixed 8 MiB device array of the library (one per
+ * GPU, kept until the process ends; its address is resolved by apsp_create)
+ * instead of the workspace.  Allocates and frees nothing; launches directly
+ * (no graph replay).  A batch whose plan does not fit (about 500 k work
+ * items: e.g. a few thousand graphs of n <= 512) is APSP_E_UNSUPPORTED,
+ * returned before anything is enqueued.  Every call on one GPU shares that
+ * array, which keeps the last call's plan: a call uploads its plan (and
+ * synchronises `stream`) when the array holds another one, and calls that
+ * overlap on one GPU -- from any context or thread -- race and must not be
+ * made.
+ */
+apsp_status_t apsp_batched_noalloc(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
+                                   void *data, const int64_t *d_offsets, const int32_t *d_sizes,
+                                   const int32_t *h_sizes, const apsp_opts_t *opts, void *stream);
+
+/*
  * Checks the input contract of an n x n matrix (Sec. 3.1 and 3.4): diagonal
  * exactly 0; int32 entries in [0, INF]; fp32 entries >= 0 and not NaN.
  * Synchronous: waits for `stream`, writes the number of violating entries to

@@ -38,7 +38,7 @@ EXPORTS = [
     "apsp_costmodel_train", "apsp_costmodel_grad",
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
     "apsp_packed16_counts", "apsp_predecessors_ex", "apsp_measure_fold_rate",
-    "apsp_workspace_size", "apsp_set_workspace", "apsp_path",
+    "apsp_workspace_size", "apsp_set_workspace", "apsp_path", "apsp_batched_noalloc",
 ]
 OP = {"solve": 0, "batched": 1, "predecessors": 2}
 FOLD = {"int32": 0, "float32": 1, "packed16": 2}
@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
             for name in ("apsp_closure", "apsp_fw", "apsp_rkleene", "apsp_square", "apsp_solve"):
                 getattr(L, name).argtypes = [vp, i32, i64, vp, i64, P(Opts), vp]
             L.apsp_batched.argtypes = [vp, i32, i32, vp, vp, vp, P(i32), P(Opts), vp]
+            L.apsp_batched_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, P(i32), P(Opts), vp]
             L.apsp_validate.argtypes = [vp, i32, i64, vp, i64, vp, P(i64)]
             L.apsp_predecessors.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp]
             L.apsp_predecessors_ex.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, i64, i32, vp]
@@ -365,6 +366,23 @@ def apsp_batched(data: torch.Tensor, offsets: torch.Tensor, sizes: torch.Tensor,
         _ensure_workspace("batched", dt, max(int(x) for x in h_sizes), count, data.device.index)
     _check(lib().apsp_batched(context(data.device.index), dt, count, data.data_ptr(), offsets.data_ptr(),
                               sizes.data_ptr(), hs, ctypes.byref(o), _stream(data, stream)))
+    return data
+
+
+def apsp_batched_noalloc(data: torch.Tensor, offsets: torch.Tensor, sizes: torch.Tensor, h_sizes,
+                         opts=None, stream=None, **kw):
+    """apsp_batched with the plan in the library's fixed device array: no
+    workspace, nothing allocated; `data` is overwritten."""
+    dt = _dtype(data)
+    if not (data.is_cuda and offsets.is_cuda and sizes.is_cuda):
+        raise TypeError("data, offsets and sizes must be device tensors")
+    if offsets.dtype != torch.int64 or sizes.dtype != torch.int32:
+        raise TypeError("offsets must be int64 and sizes int32")
+    count = len(h_sizes)
+    hs = (ctypes.c_int32 * max(count, 1))(*[int(x) for x in h_sizes])
+    o = _opts(opts, kw)
+    _check(lib().apsp_batched_noalloc(context(data.device.index), dt, count, data.data_ptr(), offsets.data_ptr(),
+                                      sizes.data_ptr(), hs, ctypes.byref(o), _stream(data, stream)))
     return data
 
 

@@ -12,8 +12,20 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
+
+// Fixed device scratch of apsp_batched_noalloc, for callers that cannot
+// allocate: each GPU the library runs on holds its own copy until the
+// process ends.  Host code never passes this name to a kernel or a copy (in
+// host code it is a stand-in, not a device address): apsp_create resolves
+// the device address once per GPU (hipGetSymbolAddress) and every use goes
+// through that address.  Word 0 is the persistent queue's ticket counter;
+// the batch plan starts at byte 256.
+constexpr size_t kFixedScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
 
 struct ProfRec {
     int kind;
@@ -29,6 +41,8 @@ struct apsp_ctx {
     char* ws = nullptr;             // caller's workspace (apsp_set_workspace)
     size_t ws_bytes = 0;
     int ws_owner = 0;               // what the workspace holds now (WS_*)
+    char* fixed = nullptr;          // device address of this GPU's fixed scratch
+    uint64_t fixed_serial = 0;      // upload serial of this context's plan in it (0: none)
     hipStream_t capture = nullptr;  // private stream used only for graph capture
     hipStream_t side = nullptr;     // second stream of the FW look-ahead
     hipEvent_t ev_a = nullptr;      // look-ahead: band r+1 current
@@ -48,7 +62,7 @@ struct apsp_ctx {
     std::vector<int4> litems;
     struct Launch { int phase, offset, count; bool side; };   // side: on the second stream
     std::vector<Launch> llaunches;
-    size_t bplan_bytes = 0;         // workspace bytes the cached plan occupies
+    uint64_t graph_key = 0;         // plan key the captured graphs were made for
     hipGraph_t lgraph = nullptr;
     hipGraphExec_t lexec = nullptr;
     // cost model
@@ -655,6 +669,58 @@ size_t batched_ws_bytes(int32_t count, size_t items)
 {
     return kWsAlign + align_up((size_t)count * sizeof(int32_t)) + align_up(std::max<size_t>(items, 1) * sizeof(int4));
 }
+// Drops the captured batched launches (after the stream has drained them).
+void drop_batch_graphs(apsp_ctx_t* ctx)
+{
+    if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
+    if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+    if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
+    if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
+    ctx->bexec = nullptr;
+    ctx->bgraph = nullptr;
+    ctx->bnode = nullptr;
+    ctx->lexec = nullptr;
+    ctx->lgraph = nullptr;
+}
+
+// Device addresses of the fixed scratch, one per GPU, and the serial of the
+// last plan uploaded into each (calls on one GPU share the array).
+struct FixedScratch {
+    char* ptr = nullptr;
+    uint64_t serial = 0;
+};
+std::mutex g_fixed_mu;
+std::map<int, FixedScratch> g_fixed;
+uint64_t g_fixed_next = 0;
+
+// Called with `device` current.
+apsp_status_t fixed_scratch_address(int device, char** out)
+{
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    FixedScratch& f = g_fixed[device];
+    if (!f.ptr) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "fixed scratch address");
+        f.ptr = static_cast<char*>(p);
+    }
+    *out = f.ptr;
+    return APSP_OK;
+}
+
+bool fixed_plan_resident(apsp_ctx_t* ctx)
+{
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    return ctx->fixed_serial != 0 && g_fixed[ctx->device].serial == ctx->fixed_serial;
+}
+
+void fixed_plan_claim(apsp_ctx_t* ctx)
+{
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    ctx->fixed_serial = ++g_fixed_next;
+    g_fixed[ctx->device].serial = ctx->fixed_serial;
+}
+
 }  // namespace
 
 extern "C" {
@@ -681,8 +747,12 @@ apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
     HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
     if (device >= count) return fail(APSP_E_ARG, "device %d of %d", device, count);
     HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    char* fixed = nullptr;
+    apsp_status_t frc = fixed_scratch_address(device, &fixed);
+    if (frc) return frc;
     apsp_ctx_t* c = new apsp_ctx_t();
     c->device = device;
+    c->fixed = fixed;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
@@ -726,10 +796,7 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     if (ctx->d_scratch) hipFree(ctx->d_scratch);
     for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
     free_costmodel(ctx);
-    if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
-    if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
-    if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
-    if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
+    drop_batch_graphs(ctx);
     if (ctx->capture) hipStreamDestroy(ctx->capture);
     if (ctx->side) hipStreamDestroy(ctx->side);
     if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
@@ -774,15 +841,7 @@ apsp_status_t apsp_set_workspace(apsp_ctx_t* ctx, void* d_ptr, size_t bytes)
     // captured batched launches point into the old workspace: let any that
     // are still running finish before they are destroyed
     if (ctx->bexec || ctx->lexec) HIP_TRY(hipDeviceSynchronize(), "workspace change sync");
-    if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
-    if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
-    if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
-    if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
-    ctx->bexec = nullptr;
-    ctx->bgraph = nullptr;
-    ctx->bnode = nullptr;
-    ctx->lexec = nullptr;
-    ctx->lgraph = nullptr;
+    drop_batch_graphs(ctx);
     ctx->bkey = 0;
     ctx->bcount = 0;
     ctx->ws = bytes ? static_cast<char*>(d_ptr) : nullptr;
@@ -1024,14 +1083,24 @@ apsp_status_t apsp_validate(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const v
     return APSP_OK;
 }
 
-apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void* data,
-                           const int64_t* d_offsets, const int32_t* d_sizes, const int32_t* h_sizes,
-                           const apsp_opts_t* opts, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Where a batched plan lives: the caller's workspace (apsp_batched) or the
+// library's fixed device scratch (apsp_batched_noalloc, no graph replay).
+struct PlanMem {
+    bool fixed;   // the fixed scratch (direct launches only)
+};
+
+apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void* data,
+                             const int64_t* d_offsets, const int32_t* d_sizes, const int32_t* h_sizes,
+                             const apsp_opts_t* opts, void* stream, PlanMem pm, const char* who)
 {
     apsp_status_t rc;
     if ((rc = check_dtype(dt))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
-    if ((rc = check_opts(o)) || (rc = reject_packed16(o, "apsp_batched"))) return rc;
+    if ((rc = check_opts(o)) || (rc = reject_packed16(o, who))) return rc;
     if (count < 0) return fail(APSP_E_ARG, "count = %d is negative", count);
     if (count > 0 && (!data || !d_offsets || !d_sizes || !h_sizes))
         return fail(APSP_E_ARG, "NULL batch pointer");
@@ -1106,26 +1175,28 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
             });
         }
     }
-    // the plan lives in the caller's workspace: [pointer record][order][items]
+    // plan memory: [pointer record][order][items], in the caller's workspace
+    // or in the fixed scratch (after its counter word)
     const size_t need = batched_ws_bytes(count, rebuild ? items.size() : ctx->litems.size());
-    if (!ctx->ws || ctx->ws_bytes < need)
-        return fail(APSP_E_NOMEM, "apsp_batched needs a workspace of %zu bytes (have %zu; apsp_workspace_size)", need,
-                    ctx->ws_bytes);
-    auto* d_bptrs = reinterpret_cast<apsp::BatchPtrs*>(ctx->ws);
-    auto* d_order = reinterpret_cast<int32_t*>(ctx->ws + kWsAlign);
-    auto* d_items = reinterpret_cast<int4*>(ctx->ws + kWsAlign + align_up((size_t)count * sizeof(int32_t)));
+    char* base;
+    if (pm.fixed) {
+        if (!ctx->fixed || need > kFixedScratchBytes - kWsAlign)
+            return fail(APSP_E_UNSUPPORTED,
+                        "%s: the batch plan needs %zu bytes, more than the fixed scratch holds (%zu); use apsp_batched",
+                        who, need, kFixedScratchBytes - kWsAlign);
+        base = ctx->fixed + kWsAlign;
+    } else {
+        if (!ctx->ws || ctx->ws_bytes < need)
+            return fail(APSP_E_NOMEM, "%s needs a workspace of %zu bytes (have %zu; apsp_workspace_size)", who, need,
+                        ctx->ws_bytes);
+        base = ctx->ws;
+    }
+    auto* d_bptrs = reinterpret_cast<apsp::BatchPtrs*>(base);
+    auto* d_order = reinterpret_cast<int32_t*>(base + kWsAlign);
+    auto* d_items = reinterpret_cast<int4*>(base + kWsAlign + align_up((size_t)count * sizeof(int32_t)));
     if (rebuild) {
-        // a replay of the previous plan may still be running
-        if (ctx->bexec || ctx->lexec) HIP_TRY(hipStreamSynchronize(st), "plan change sync");
-        if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
-        if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
-        if (ctx->lexec) hipGraphExecDestroy(ctx->lexec);
-        if (ctx->lgraph) hipGraphDestroy(ctx->lgraph);
-        ctx->bexec = nullptr;
-        ctx->bgraph = nullptr;
-        ctx->bnode = nullptr;
-        ctx->lexec = nullptr;
-        ctx->lgraph = nullptr;
+        // the captured graphs (workspace path) belong to the previous plan;
+        // they are dropped by the next call that would replay them
         ctx->border = std::move(order);
         ctx->litems = std::move(items);
         ctx->llaunches = std::move(launches);
@@ -1133,8 +1204,16 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
         ctx->bcount = count;
         ctx->bdtype = dt;
         ctx->ws_owner = WS_NONE;
+        ctx->fixed_serial = 0;
     }
-    if (ctx->ws_owner != WS_BATCHED) {
+    if (!pm.fixed && ctx->graph_key != ctx->bkey && (ctx->bexec || ctx->lexec)) {
+        // a replay of the previous plan may still be running
+        HIP_TRY(hipStreamSynchronize(st), "plan change sync");
+        drop_batch_graphs(ctx);
+    }
+    if (!pm.fixed) ctx->graph_key = ctx->bkey;
+    const bool resident = pm.fixed ? fixed_plan_resident(ctx) : ctx->ws_owner == WS_BATCHED;
+    if (!resident) {
         // (re)upload the plan; the host vectors stay alive in the context, and
         // the stream is synchronised so that no later plan replaces them while
         // the copy may still read them (new batch shapes only)
@@ -1146,8 +1225,10 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
                                    hipMemcpyHostToDevice, st),
                     "plan upload");
         HIP_TRY(hipStreamSynchronize(st), "plan upload sync");
-        ctx->ws_owner = WS_BATCHED;
-        ctx->bplan_bytes = need;
+        if (pm.fixed)
+            fixed_plan_claim(ctx);
+        else
+            ctx->ws_owner = WS_BATCHED;
     }
     apsp::BatchArgs a{};
     a.data = data;
@@ -1155,7 +1236,7 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
     a.sizes = d_sizes;
     a.order = d_order;
     a.count = count;
-    a.counter = static_cast<uint32_t*>(ctx->d_scratch) + 8;
+    a.counter = pm.fixed ? reinterpret_cast<uint32_t*>(ctx->fixed) : static_cast<uint32_t*>(ctx->d_scratch) + 8;
     const apsp::DType kdt = (apsp::DType)dt;
     const int grid = std::min<int>(count, ctx->num_cus * apsp::batched_resident_per_cu(kdt));
     const double terms = 0.0, bytes = 0.0;
@@ -1193,7 +1274,7 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
             HIP_TRY(apsp::launch_batch_ptrs(d_bptrs, data, d_offsets, d_sizes, st), "batch pointer update");
             // a one-launch schedule (every graph n <= 128) runs faster as a
             // direct launch than as a graph replay
-            if ((o->flags & APSP_FLAG_BATCH_NO_GRAPH) || ctx->llaunches.size() <= 1) {
+            if (pm.fixed || (o->flags & APSP_FLAG_BATCH_NO_GRAPH) || ctx->llaunches.size() <= 1) {
                 HIP_TRY(enqueue(st), "lock-step launch");
                 return APSP_OK;
             }
@@ -1234,7 +1315,7 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
         }
         return APSP_OK;
     }
-    if (o->flags & APSP_FLAG_BATCH_NO_GRAPH) {
+    if (pm.fixed || (o->flags & APSP_FLAG_BATCH_NO_GRAPH)) {
         return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
             HIP_TRY(apsp::launch_batched(kdt, a, grid, st), "batched launch");
             return APSP_OK;
@@ -1296,6 +1377,26 @@ apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void
         HIP_TRY(hipGraphLaunch(ctx->bexec, st), "graph launch");
         return APSP_OK;
     });
+}
+
+}  // namespace
+
+extern "C" {
+
+apsp_status_t apsp_batched(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void* data,
+                           const int64_t* d_offsets, const int32_t* d_sizes, const int32_t* h_sizes,
+                           const apsp_opts_t* opts, void* stream)
+{
+    return batched_common(ctx, dt, count, data, d_offsets, d_sizes, h_sizes, opts, stream, PlanMem{false},
+                          "apsp_batched");
+}
+
+apsp_status_t apsp_batched_noalloc(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, void* data,
+                                   const int64_t* d_offsets, const int32_t* d_sizes, const int32_t* h_sizes,
+                                   const apsp_opts_t* opts, void* stream)
+{
+    return batched_common(ctx, dt, count, data, d_offsets, d_sizes, h_sizes, opts, stream, PlanMem{true},
+                          "apsp_batched_noalloc");
 }
 
 apsp_status_t apsp_profile_enable(apsp_ctx_t* ctx, int32_t on)
