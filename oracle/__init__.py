@@ -11,6 +11,8 @@ Contents (paper: arXiv 2310.03983, "The Floyd-Warshall Algorithm
 Re-implemented Using 3D-Tensors and Hardware Acceleration"):
 
 * ``fw_i32`` / ``fw_f64``         -- triple-loop Floyd-Warshall, Sec. 2 Eq. 1 (C).
+* ``fw_i32_steps``                -- passes k0 .. k1-1 of that loop (C); a bounded
+  sample for timing, pinned by the restricted-intermediate invariant.
 * ``minplus_i32`` / ``minplus_f32`` -- accumulating min-plus product, Sec. 3
   Eq. 2 (C): ``C <- min(C, A (min,+) B)``.
 * ``dijkstra_i32`` / ``dijkstra_f64`` -- per-source Dijkstra (C); an algorithm
@@ -64,6 +66,8 @@ def _load():
             i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
             lib.oracle_fw_i32.argtypes = [i64, vp, i64, i32]
             lib.oracle_fw_i32.restype = None
+            lib.oracle_fw_i32_steps.argtypes = [i64, vp, i64, i64, i64, i32]
+            lib.oracle_fw_i32_steps.restype = None
             lib.oracle_fw_f64.argtypes = [i64, vp, i64, i32]
             lib.oracle_fw_f64.restype = None
             lib.oracle_minplus_i32.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64]
@@ -87,7 +91,15 @@ def _ptr(a: np.ndarray) -> int:
 
 
 def default_threads() -> int:
-    return max(1, min(os.cpu_count() or 1, 16))
+    """The host threads the oracle uses: OMP_NUM_THREADS when set (the share
+    of the host a job is given), else every core the process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
 
 
 # ---------------------------------------------------------------------------
@@ -100,6 +112,17 @@ def fw_i32(W: np.ndarray, threads: int = 1) -> np.ndarray:
     n = D.shape[0]
     assert D.shape == (n, n)
     _load().oracle_fw_i32(n, _ptr(D), n, threads)
+    return D
+
+
+def fw_i32_steps(D: np.ndarray, k0: int, k1: int, threads: int = 1) -> np.ndarray:
+    """Passes k0 .. k1-1 of the Eq. 1 recurrence applied to a copy of D (int32):
+    from W, passes 0 .. k-1 leave the shortest distances whose intermediate
+    vertices all lie below k."""
+    D = np.array(D, dtype=np.int32, order="C", copy=True)
+    n = D.shape[0]
+    assert D.shape == (n, n)
+    _load().oracle_fw_i32_steps(n, _ptr(D), n, k0, k1, threads)
     return D
 
 

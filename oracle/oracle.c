@@ -58,6 +58,25 @@ void oracle_fw_i32(int64_t n, int32_t *d, int64_t ld, int nthreads)
     }
 }
 
+/* Passes k0 .. k1-1 of the same recurrence, in place: after passes 0 .. k-1
+ * from W, d[i][j] is the shortest i -> j distance over paths whose
+ * intermediate vertices all lie below k (the invariant behind Eq. 1).  Used
+ * to time a bounded sample of the full triple loop (every pass does exactly
+ * n^2 updates). */
+void oracle_fw_i32_steps(int64_t n, int32_t *d, int64_t ld, int64_t k0, int64_t k1, int nthreads)
+{
+    for (int64_t k = k0; k < k1 && k < n; ++k) {
+#pragma omp parallel for num_threads(nthreads > 0 ? nthreads : 1) schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t dik = d[i * ld + k];
+            for (int64_t j = 0; j < n; ++j) {
+                int64_t via = sat_add_i32(dik, d[k * ld + j]);
+                if (via < d[i * ld + j]) d[i * ld + j] = (int32_t)via;
+            }
+        }
+    }
+}
+
 void oracle_fw_f64(int64_t n, double *d, int64_t ld, int nthreads)
 {
     for (int64_t k = 0; k < n; ++k) {

@@ -59,6 +59,45 @@ def test_fw_vs_bruteforce_int(oracle):
         np.testing.assert_array_equal(oracle.fw_i32(W), ref, err_msg=f"trial {trial}")
 
 
+def restricted_bruteforce(W, k):
+    """Shortest i -> j distance over simple paths whose intermediate vertices
+    all lie below k (enumerated; tiny n), saturated at INF."""
+    n = len(W)
+    out = np.full((n, n), INF, dtype=np.int64)
+    for s in range(n):
+        out[s, s] = 0
+
+        def dfs(u, dist, seen):
+            for v in range(n):
+                if v in seen or W[u][v] >= INF:
+                    continue
+                nd = dist + int(W[u][v])
+                if nd < out[s, v]:
+                    out[s, v] = min(nd, INF)
+                if v < k:                       # only vertices below k may be passed through
+                    dfs(v, nd, seen | {v})
+
+        dfs(s, 0, {s})
+    return out
+
+
+def test_fw_steps_restricted_intermediates(oracle):
+    """After passes 0 .. k-1 of Eq. 1, D holds the shortest distances over
+    paths with every intermediate vertex below k (brute force); the passes
+    compose (0..a then a..n equals the full triple loop)."""
+    rng = np.random.default_rng(13)
+    for trial in range(60):
+        n = int(rng.integers(1, 8))
+        W = rand_graph(rng, n, float(rng.choice([0.3, 0.6])), 1, int(rng.choice([9, 1000])))
+        for k in range(n + 1):
+            np.testing.assert_array_equal(oracle.fw_i32_steps(W, 0, k), restricted_bruteforce(W.tolist(), k),
+                                          err_msg=f"trial {trial} k={k}")
+    W = rand_graph(rng, 90, 0.05, 1, 100)
+    for a in (0, 1, 37, 90):
+        np.testing.assert_array_equal(oracle.fw_i32_steps(oracle.fw_i32_steps(W, 0, a), a, 90, threads=3),
+                                      oracle.fw_i32(W))
+
+
 def test_fw_f64_vs_bruteforce(oracle):
     rng = np.random.default_rng(12)
     for trial in range(100):
