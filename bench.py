@@ -3,27 +3,35 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-One step is one complete APSP solve (R-Kleene: tile closures, panel and
-remainder min-plus products) of the n=16384, p=0.01 directed graph with
-int32 costs uniform in [1, 1000] (INF = 2^30).  The K + W input copies are
+One step is one complete APSP solve of the n=16384, p=0.01 directed graph
+with int32 costs uniform in [1, 1000] (INF = 2^30), as the library runs it by
+default: apsp_solve with no options, so the shipped cost model plans the
+solve from the matrix (one device feature pass and one scoring read-back
+inside the step) and the chosen candidate runs.  The K + W input copies are
 generated once and placed in HBM before timing, so the timed region contains
 only the solves.  Prints one JSON line.
 
 Reported alongside the headline:
-  roofline     -- the dominant kernel (int32 min-plus product, 128 x 128
-                  tiles): algorithmic VALU ops (2 per min-plus term: one add,
-                  one min) per launch / its average launch duration, timed
-                  with HIP events on the launch stream during the timed steps;
-  measured_ceiling -- the same kernel's achieved rate against the fold's
-                  issue rate measured by a spin kernel on the device (and that
-                  rate per lane and ns: the clock, at one lane-instruction per
-                  cycle);
-  panel_phase  -- the FW panel products (64 x 64 tiles, K = 128) of the same
-                  solve: compulsory HBM bytes / event-timed duration, GB/s
-                  against the 8 TB/s HBM peak (recorded in one more solve);
-  cpu_baseline -- the CPU oracle (per-source Dijkstra, OpenMP over sources)
-                  on a bounded sample of sources of the same graph,
-                  extrapolated to the full APSP.
+  roofline     -- the dominant kernel (the min-plus product with 128 x 128
+                  tiles, in the arithmetic the plan uses): algorithmic ops
+                  (2 per min-plus term: one add, one min) per launch / its
+                  average launch duration, timed with HIP events on the
+                  launch stream during the timed steps, against MI355X's
+                  published vector peak (157.3 T ops/s: 256 CUs x 4 SIMDs x
+                  16 lanes x 2.4 GHz x 4 ops per lane and cycle);
+                  fold_ceiling gives the same rate against the issue ceiling
+                  of the fold's own instructions;
+  measured_ceiling -- the same against the fold's issue rate measured by a
+                  spin kernel on the device;
+  panel_phase  -- the FW panel products (64 x 64 tiles, K = 128):
+                  compulsory HBM bytes / event-timed duration, GB/s against
+                  the 8 TB/s HBM peak (recorded in one more solve);
+  cpu_baseline -- the CPU oracle as it stands on the host's cores: the Eq. 1
+                  triple loop over a bounded sample of its k passes at
+                  n = 16384 (every pass does n^2 updates), scaled to n
+                  passes; plus the full triple loop at n = 256 (one thread
+                  and all threads) and n = 4096, and Dijkstra from 64
+                  sources of the headline graph.
 """
 from __future__ import annotations
 
@@ -39,6 +47,8 @@ sys.path.insert(0, ROOT)
 METRIC = "APSP n³ updates/s & % VALU roofline at n=16384 int32; batched graphs/s"
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 32-bit VALU lane-instructions/s
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X's published vector peak (fp32, 157.3 TFLOP/s): 4 operations per lane and cycle
+PUBLISHED_PEAK_OPS = 157.3e12
 # Algorithmic operations (an add and a min per term) done by one lane-instruction
 # of the fold: int32 -- one v_lshl_add_u64 forms two sums, one v_min3_u32 takes
 # two minima: 2; capped 16-bit -- one 64-bit add forms four sums and one
@@ -52,12 +62,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n16384_p0.01_i32")
-    ap.add_argument("--algo", default="rkleene", choices=["rkleene", "fw", "solve"])
+    ap.add_argument("--algo", default="solve", choices=["solve", "rkleene", "fw"],
+                    help="solve: the library's default (cost-model plan); rkleene / fw: that solver with int32 "
+                         "products (or --packed16)")
     ap.add_argument("--cutover", type=int, default=4096,
                     help="R-Kleene: sub-problems of at most this size use blocked FW")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="target CPU time of the n=16384 triple-loop sample")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-graph batched measurement")
     ap.add_argument("--batched-steps", type=int, default=20)
@@ -115,6 +127,29 @@ def bench_packed16(torch, apsp, Wd, n, cutover):
             "minplus128_terms_per_s": k["terms"] / (k["ms"] / 1e3) if k["ms"] else None,
             "note": "int32 in and out; products fold 4 terms in 2 instructions (capped 16-bit); "
                     "exact, checked by counting capped entries after the solve"}
+
+
+def bench_int32_products(torch, apsp, Wd, n, cutover):
+    """The headline graph through R-Kleene (4096 FW cutover) with int32
+    products: time per solve and the 128 x 128 product's roofline."""
+    def fn(d):
+        apsp.apsp_rkleene(d, cutover=cutover)
+    ins = [Wd.clone() for _ in range(4)]
+    fn(ins[0])
+    torch.cuda.synchronize()
+    fold = apsp.apsp_measure_fold_rate("int32")
+    apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_128])
+    t0 = time.perf_counter()
+    for d in ins[1:]:
+        fn(d)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / 3
+    k = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_128)
+    apsp.apsp_profile_enable(False)
+    del ins
+    torch.cuda.empty_cache()
+    return {"ms_per_step": t * 1e3, "updates_per_s": n ** 3 / t, "valu_frac_whole_solve": 2 * n ** 3 / t / PUBLISHED_PEAK_OPS,
+            "roofline": roofline(k, False, fold)}
 
 
 def bench_small(torch, apsp, gg, dev):
@@ -246,6 +281,51 @@ def bench_batched(torch, np, apsp, gg, dev, steps):
     return out
 
 
+def roofline(k, packed, fold_rate):
+    """Dominant-kernel roofline from the event-timed launches of the timed
+    steps: achieved = 2 ops per term x terms per launch / average launch
+    time, against the published 157.3 T ops/s; fold_ceiling against the
+    issue ceiling of the fold's own instructions (int32: 2 ops per
+    lane-instruction, 78.6 T; capped 16-bit: 4, 157.3 T); measured_ceiling
+    against the spin kernel's rate."""
+    launches = max(k["launches"], 1)
+    avg_ms = k["ms"] / launches
+    ops_per_launch = 2.0 * k["terms"] / launches
+    achieved = ops_per_launch / (avg_ms / 1e3)
+    fold_peak = VALU_PEAK_OPS * OPS_PER_INSTR[packed]
+    return {
+        "bound": "alu",
+        "kernel": "k_minplus<int32 data, capped 16-bit products, 128x128 tile>" if packed
+                  else "k_minplus<int32, 128x128 tile>",
+        "achieved": achieved / 1e12,
+        "peak": PUBLISHED_PEAK_OPS / 1e12,
+        "unit": "Tops/s",
+        "frac": achieved / PUBLISHED_PEAK_OPS,
+        "traffic": counter_traffic(packed),
+        "launches": k["launches"],
+        "avg_launch_ms": avg_ms,
+        "ops_per_launch": ops_per_launch,
+        "note": "achieved: 2 algorithmic ops per min-plus term (add + min) x terms per launch / event-timed "
+                "average launch duration; peak: MI355X's published vector peak (256 CUs x 64 lanes x 2.4 GHz x "
+                "4 ops per lane and cycle = 157.3e12)",
+        "fold_ceiling": {
+            "peak": fold_peak / 1e12,
+            "frac": achieved / fold_peak,
+            "note": ("capped 16-bit fold: one 64-bit add forms four sums and one v_pk_minimum3_f16 takes four "
+                     "minima, 4 ops per lane-instruction (the same 157.3e12)") if packed else
+                    ("int32 fold: one v_lshl_add_u64 forms two sums and one v_min3_u32 takes two minima, 2 ops per "
+                     "lane-instruction: 39.3e12 lane-instructions/s x 2 = 78.6e12, half the published peak"),
+        },
+        "measured_ceiling": {
+            "what": "spin kernel repeating the fold's own instructions on registers over the whole device "
+                    "(apsp_measure_fold_rate), before and after the timed steps; the higher rate is used",
+            "terms_per_s": fold_rate["terms_per_s"],
+            "lane_instr_per_lane_per_ns": fold_rate["lane_instr_per_s"] / (256 * 64) / 1e9,
+            "frac": achieved / (2.0 * fold_rate["terms_per_s"]),
+        },
+    }
+
+
 def counter_traffic(packed16=False):
     """HBM bytes per launch of the 128x128 product kernel from the committed
     rocprofv3 counter summary, or None when the kernel sources have changed
@@ -265,22 +345,36 @@ def counter_traffic(packed16=False):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def cpu_baseline(W, sources_all, n, target_s):
-    """The oracle as it stands: Dijkstra from a sample of sources, OpenMP
-    over sources on the host cores, extrapolated to all n sources.  The
-    sample grows until one call takes about target_s seconds."""
+def cpu_baseline(W, n, sources, target_s, gg):
+    """The oracle as it stands, on the host threads this job is given
+    (OMP_NUM_THREADS, else every core the process may run on): the Eq. 1
+    triple loop over its first k passes at the headline size, k grown until
+    the sample takes about target_s (every pass does n^2 updates, so
+    n^3 / (t_sample * n / k) is the full loop's rate); the full triple loop
+    at n = 256 (one thread and all threads) and n = 4096 (all threads); and
+    Dijkstra from 64 sources of the headline graph."""
     import oracle
     threads = oracle.default_threads()
-    count = threads
+    k = 8
     while True:
         t0 = time.perf_counter()
-        oracle.dijkstra_i32(W, sources_all[:count], threads=threads)
+        oracle.fw_i32_steps(W, 0, k, threads=threads)
         t = time.perf_counter() - t0
-        if t >= 0.5 * target_s or count >= len(sources_all):
+        if t >= 0.5 * target_s or k >= n:
             break
-        grow = max(2.0, min(8.0, target_s / max(t, 1e-3)))
-        count = min(len(sources_all), int(count * grow) // threads * threads)
-    t_full = t * n / count
+        k = min(n, int(k * max(2.0, min(8.0, target_s / max(t, 1e-3)))))
+    t_full = t * n / k
+    legs = {}
+    W256 = gg.SINGLE["n256_p0.1_i32"].make()
+    for label, thr in (("fw_n256_1_thread", 1), ("fw_n256_all_threads", threads)):
+        best = min(_timed(lambda: oracle.fw_i32(W256, threads=thr)) for _ in range(3))
+        legs[label] = {"s": best, "updates_per_s": 256 ** 3 / best, "threads": thr}
+    W4k = gg.SINGLE["n4096_p0.05_i32"].make()
+    t4 = _timed(lambda: oracle.fw_i32(W4k, threads=threads))
+    legs["fw_n4096_all_threads"] = {"s": t4, "updates_per_s": 4096 ** 3 / t4, "threads": threads}
+    td = _timed(lambda: oracle.dijkstra_i32(W, sources, threads=threads))
+    legs["dijkstra_n16384_64_sources"] = {"s": td, "sources": len(sources), "threads": threads,
+                                          "full_apsp_s_extrapolated": td * n / len(sources)}
     cpu_model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -288,10 +382,18 @@ def cpu_baseline(W, sources_all, n, target_s):
     except OSError:
         pass
     return {"value": n ** 3 / t_full, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "cpu_model": cpu_model,
-            "sample": f"Dijkstra (binary heap, OpenMP over sources) from {count} of {n} seeded sources of the "
-                      f"same graph in {t:.1f} s; full APSP extrapolated x{n / count:.1f} = {t_full:.0f} s; "
-                      f"value = n^3 / extrapolated time"}
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model,
+            "sample": f"Eq. 1 triple loop (int32, OpenMP over rows) on the headline graph: passes 0..{k - 1} of "
+                      f"{n} in {t:.2f} s on {threads} threads (the job's host share; the host has "
+                      f"{os.cpu_count()} CPUs); every pass does n^2 updates, so the full loop takes "
+                      f"{t_full:.0f} s; value = n^3 / that time",
+            "legs": legs}
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
 
 
 def main():
@@ -317,7 +419,12 @@ def main():
     solve0 = {"rkleene": apsp.apsp_rkleene, "fw": apsp.apsp_fw, "solve": apsp.apsp_solve}[args.algo]
 
     def solve(d, **kw):
+        if args.algo == "solve" and not kw and not args.packed16:
+            return apsp.apsp_solve(d)          # every option automatic: the cost model plans
+        if args.algo != "fw":
+            kw.setdefault("cutover", args.cutover)
         return solve0(d, packed16=args.packed16, **kw)
+
     copies = [Wd.clone() for _ in range(args.steps + args.warmup)]
     # calibration for the HBM byte counters: one elementwise kernel that
     # reads n*n*4 bytes and writes n*n*4 bytes (outside the timed region)
@@ -327,37 +434,50 @@ def main():
 
     # timed region: K solves on resident inputs; HIP events bracket only the
     # dominant kernel (recording every launch would perturb the timing)
-    log(f"timing {args.steps} steps ({args.algo}, cutover {args.cutover}) after {args.warmup} warm-up")
-    for s in range(args.warmup):
-        solve(copies[s], cutover=args.cutover)
+    log(f"timing {args.steps} steps ({args.algo}) after {args.warmup} warm-up")
+    for s_ in range(args.warmup):
+        solve(copies[s_])
     torch.cuda.synchronize()
-    fold_kind = "packed16" if args.packed16 else "int32"
+    choice = apsp.apsp_solve_choice() if args.algo == "solve" else None
+    plan = apsp.apsp_candidate(choice) if choice is not None and choice >= 0 else None
+    packed = args.packed16 or bool(plan is not None and plan.flags & apsp.FLAG_PACKED16)
+    fold_kind = "packed16" if packed else "int32"
     fold_before = apsp.apsp_measure_fold_rate(fold_kind)
     apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_128])
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        solve(copies[args.warmup + s], cutover=args.cutover)
+    for s_ in range(args.steps):
+        solve(copies[args.warmup + s_])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     k128 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_128)
     apsp.apsp_profile_enable(False)
+    # the result of the timed solves equals the int32 solver's (exactness of
+    # the plan's arithmetic, checked outside the timed region)
+    ref = Wd.clone()
+    apsp.apsp_rkleene(ref, cutover=args.cutover)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(ref, copies[args.warmup]))
+    del ref
     # one extra, untimed solve with every launch bracketed: time shares
     share_in = copies[0]
     share_in.copy_(Wd)
     apsp.apsp_profile_enable(True)
-    solve(share_in, cutover=args.cutover)
+    solve(share_in)
     torch.cuda.synchronize()
     shares = {k: apsp.apsp_profile_read(v) for k, v in (("minplus_128", apsp.KERNEL_MINPLUS_128),
                                                       ("minplus_64", apsp.KERNEL_MINPLUS_64),
-                                                      ("closure", apsp.KERNEL_CLOSURE))}
+                                                      ("closure", apsp.KERNEL_CLOSURE),
+                                                      ("other", apsp.KERNEL_OTHER))}
     apsp.apsp_profile_enable(False)
     # panel phase: the 64x64 panel products of the FW windows, recorded alone
-    # in one more solve without look-ahead (with it they overlap the
-    # remainder on the second stream, and their event durations would
-    # include waiting for CUs)
+    # in one more solve of the same plan without look-ahead (with it they
+    # overlap the remainder on the second stream, and their event durations
+    # would include waiting for CUs)
     share_in.copy_(Wd)
+    pkw = {"cutover": plan.cutover, "packed16": bool(plan.flags & apsp.FLAG_PACKED16)} if plan is not None and \
+        plan.algo == 2 else {"cutover": args.cutover, "packed16": args.packed16}
     apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_64])
-    solve(share_in, cutover=args.cutover, lookahead=False)
+    apsp.apsp_rkleene(share_in, lookahead=False, **pkw)
     torch.cuda.synchronize()
     k64 = apsp.apsp_profile_read(apsp.KERNEL_MINPLUS_64)
     apsp.apsp_profile_enable(False)
@@ -370,9 +490,6 @@ def main():
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = n ** 3 / (ms_per_step / 1e3)
-    avg_ms = k128["ms"] / max(k128["launches"], 1)
-    ops_per_launch = 2.0 * k128["terms"] / max(k128["launches"], 1)
-    achieved = ops_per_launch / (avg_ms / 1e3)
     result = {
         "metric": METRIC,
         "value": value,
@@ -384,53 +501,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16x2 capped (int32 in/out)" if args.packed16 else "int32",
+        "dtype": "u16 capped, exact int32 result" if packed else "int32",
         "data": "synthetic (seeded Bernoulli graph generator)",
-        "config": {"workload": f"apsp_{wl.name}_{args.algo}" + ("_packed16" if args.packed16 else ""),
-                   "n": n, "p": wl.p, "cutover": args.cutover,
-                   "weights": f"int32 uniform [{int(wl.lo)}, {int(wl.hi)}]", "inf": 2 ** 30,
+        "config": {"workload": f"apsp_{wl.name}_" + ("default_solve" if args.algo == "solve" else args.algo) +
+                               ("_packed16" if args.packed16 else ""),
+                   "n": n, "p": wl.p, "weights": f"int32 uniform [{int(wl.lo)}, {int(wl.hi)}]", "inf": 2 ** 30,
+                   "plan": None if plan is None else
+                   {"candidate": choice, "algo": {1: "fw", 2: "rkleene", 3: "square"}[plan.algo],
+                    "block": plan.block, "cutover": plan.cutover,
+                    "products": "capped 16-bit" if plan.flags & apsp.FLAG_PACKED16 else "int32"},
                    "parallelism": "single GPU"},
-        # the headline's basis: 2 ops per term at one op per lane-instruction
-        "valu_roofline_frac": 2.0 * value / VALU_PEAK_OPS,
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_minplus<int32 data, capped 16-bit products, 128x128 tile>" if args.packed16
-                      else "k_minplus<int32, 128x128 tile>",
-            "achieved": achieved / 1e12,
-            "peak": VALU_PEAK_OPS * OPS_PER_INSTR[args.packed16] / 1e12,
-            "unit": "Tops/s",
-            "frac": achieved / (VALU_PEAK_OPS * OPS_PER_INSTR[args.packed16]),
-            "traffic": counter_traffic(args.packed16),
-            "launches": k128["launches"],
-            "avg_launch_ms": avg_ms,
-            "ops_per_launch": ops_per_launch,
-            "peak_lane_instr": VALU_PEAK_OPS / 1e12,
-            "ops_per_lane_instr": OPS_PER_INSTR[args.packed16],
-            "note": ("achieved: 2 algorithmic ops per min-plus term (add + min); peak: 39.32e12 VALU "
-                     "lane-instructions/s x the 4 ops one lane-instruction of the fold performs (one 64-bit add "
-                     "forms four 16-bit sums, one v_pk_minimum3_f16 takes four minima)")
-                    if args.packed16 else
-                    ("achieved: 2 algorithmic ops per min-plus term (add + min); peak: 39.32e12 VALU "
-                     "lane-instructions/s x the 2 ops one lane-instruction of the fold performs (one 64-bit add "
-                     "forms two 32-bit sums, one v_min3_u32 takes two minima)"),
-        },
-        "measured_ceiling": {
-            "what": "spin kernel repeating the fold's own instructions on registers over the whole device "
-                    "(apsp_measure_fold_rate), run before and after the timed steps; the higher rate is used. "
-                    "A pure-VALU spin draws more power than the product kernel, so its clock can be lower "
-                    "and frac can approach or pass 1",
-            "terms_per_s_before": fold_before["terms_per_s"],
-            "terms_per_s_after": fold_after["terms_per_s"],
-            "terms_per_s": fold_rate["terms_per_s"],
-            "lane_instr_per_s": fold_rate["lane_instr_per_s"],
-            # equals the clock in GHz when the fold issues one lane-instruction per lane and cycle
-            "lane_instr_per_lane_per_ns": fold_rate["lane_instr_per_s"] / (256 * 64) / 1e9,
-            "frac": achieved / (2.0 * fold_rate["terms_per_s"]),
-        },
+        "result_equals_int32_rkleene": same,
+        # the whole solve's rate against the published peak, 2 ops per term
+        "valu_frac_whole_solve": 2.0 * value / PUBLISHED_PEAK_OPS,
+        "roofline": roofline(k128, packed, fold_rate),
         "panel_phase": {
-            "kernel": "k_minplus<int32, 64x64 tile>" + (" (capped 16-bit)" if args.packed16 else ""),
-            "what": "FW panel products of the 4096 windows (row and column panels, K = 128), in a solve "
-                    "without look-ahead so that each launch runs alone",
+            "kernel": "k_minplus<64x64 tile>" + (" (capped 16-bit)" if pkw["packed16"] else " (int32)"),
+            "what": "FW panel products of the R-Kleene cutover windows (row and column panels, K = 128), in a "
+                    "solve without look-ahead so that each launch runs alone",
             "launches_per_solve": k64["launches"],
             "ms_per_solve": k64["ms"],
             "bytes_per_launch": k64["bytes"] / max(k64["launches"], 1),
@@ -459,6 +547,7 @@ def main():
             del ins, src
             torch.cuda.empty_cache()
         extras["rkleene_i32_packed16"] = bench_packed16(torch, apsp, Wd, n, args.cutover)
+        extras["rkleene_i32"] = bench_int32_products(torch, apsp, Wd, n, args.cutover)
         extras.update(bench_small(torch, apsp, gg, dev))
         extras["fold_rates"] = {k: apsp.apsp_measure_fold_rate(k) for k in ("int32", "float32", "packed16")}
         if Wd.dtype == torch.int32:
@@ -478,8 +567,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        srcs = gg.dijkstra_sources(n, wl.seed(), count=min(n, 4096))
-        result["cpu_baseline"] = cpu_baseline(W, srcs, n, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(W, n, wl.sources(), args.cpu_seconds, gg)
 
     print(json.dumps(result), flush=True)
     return 0

@@ -130,8 +130,12 @@ const char *apsp_version(void);
  * edge list) need device memory beyond their arguments; the caller provides
  * it once with apsp_set_workspace and the library never allocates it.
  * apsp_workspace_size returns the bytes an operation needs:
- *   APSP_OP_SOLVE         apsp_fw / apsp_rkleene / apsp_square / apsp_solve /
- *                         minplus_gemm / apsp_closure / apsp_validate: 0;
+ *   APSP_OP_SOLVE         n_or_total = n: the feature pass of apsp_features
+ *                         and of apsp_solve's cost-model plan (one int32 per
+ *                         vertex; without it apsp_solve keeps the size
+ *                         rule); apsp_fw / apsp_rkleene / apsp_square /
+ *                         minplus_gemm / apsp_closure / apsp_validate need
+ *                         no workspace;
  *   APSP_OP_BATCHED       n_or_total = the largest n of the batch, count = the
  *                         number of graphs: an upper bound for any batch of
  *                         that shape;
@@ -238,12 +242,36 @@ apsp_status_t apsp_square(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
  */
 apsp_status_t apsp_packed16_counts(apsp_ctx_t *ctx, int64_t *runs, int64_t *redone);
 
-/* Dispatches to apsp_fw / apsp_rkleene / apsp_square per opts->algo; with
- * APSP_ALGO_AUTO (or opts == NULL) the size rule decides: blocked FW up to
- * n = 4096, R-Kleene with a 4096 FW cutover above.  (apsp_plan gives the
- * cost model's choice for explicit use.) */
+/* Dispatches to apsp_fw / apsp_rkleene / apsp_square per opts->algo.  With
+ * every option automatic (opts == NULL or all fields 0), a cost model whose
+ * K equals apsp_candidate_count() loaded (apsp_costmodel_load / _set_params)
+ * and a workspace of apsp_workspace_size(APSP_OP_SOLVE, n), the cost model
+ * plans the solve from the matrix itself: one pass over D computes the four
+ * features (as apsp_features), the inference kernel scores every candidate,
+ * and the scores are read back (`stream` is synchronised once); the solve
+ * then runs the best candidate the dtype can run.  Otherwise (or with any
+ * option set) the size rule decides: blocked FW up to n = 4096, R-Kleene
+ * with a 4096 FW cutover above, keeping the given options. */
 apsp_status_t apsp_solve(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                          void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/* Candidate index the last automatic apsp_solve on this context ran (-1 when
+ * the size rule decided). */
+apsp_status_t apsp_solve_choice(apsp_ctx_t *ctx, int32_t *h_choice);
+
+/*
+ * The cost model's four inputs for the n x n cost matrix D (see
+ * apsp_costmodel_init): log2 n, log10 density with density = m / (n (n-1))
+ * and m the finite off-diagonal entries (clamped to 1e-9), log2 of the batch
+ * (0 here), and 1 when the graph is weakly connected (edges taken as
+ * undirected; a lock-free union-find over the edges in the workspace) else
+ * 0.  Synchronous: one pass over D, then the four floats are read back into
+ * h_features.  Needs a workspace of apsp_workspace_size(APSP_OP_SOLVE, n)
+ * bytes (APSP_E_NOMEM otherwise); with apsp_plan a C caller plans from a
+ * matrix alone.
+ */
+apsp_status_t apsp_features(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n, const void *D, int64_t ldd,
+                            void *stream, float *h_features);
 
 /*
  * Last-hop predecessors (Sec. 2: pred[i][j] is the vertex before j on the

@@ -39,7 +39,10 @@ EXPORTS = [
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
     "apsp_packed16_counts", "apsp_predecessors_ex", "apsp_measure_fold_rate",
     "apsp_workspace_size", "apsp_set_workspace", "apsp_path", "apsp_batched_noalloc",
+    "apsp_features", "apsp_solve_choice",
 ]
+# the trained cost model shipped with the package (plain-text model file)
+MODEL_PATH = os.path.join(_PKG, "data", "costmodel_mlp.txt")
 OP = {"solve": 0, "batched": 1, "predecessors": 2}
 FOLD = {"int32": 0, "float32": 1, "packed16": 2}
 PRED = {"auto": 0, "dense": 1, "sparse": 2}
@@ -137,6 +140,8 @@ def lib() -> ctypes.CDLL:
             L.apsp_workspace_size.argtypes = [vp, i32, i32, i64, i32]
             L.apsp_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
             L.apsp_path.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, i32, vp, vp]
+            L.apsp_features.argtypes = [vp, i32, i64, vp, i64, vp, P(ctypes.c_float)]
+            L.apsp_solve_choice.argtypes = [vp, P(i32)]
             for name in EXPORTS:
                 if name not in ("apsp_last_error", "apsp_version", "apsp_workspace_size"):
                     getattr(L, name).restype = i32
@@ -165,6 +170,9 @@ def context(device: int | None = None) -> ctypes.c_void_p:
         _check(lib().apsp_create(ctypes.byref(c), device))
         with _lock:
             _ctxs[device] = c
+        # the shipped cost model plans apsp_solve's automatic choice
+        if os.path.exists(MODEL_PATH) and os.environ.get("APSP_NO_MODEL") != "1":
+            _check(lib().apsp_costmodel_load(c, os.fsencode(MODEL_PATH)))
     return c
 
 
@@ -278,8 +286,31 @@ def apsp_square(D, opts=None, stream=None, **kw):
 
 
 def apsp_solve(D, opts=None, stream=None, **kw):
-    """Planner-selected algorithm; D is overwritten."""
+    """Planner-selected algorithm; D is overwritten.  With no options the
+    context's cost model plans from the matrix (a workspace for the feature
+    pass is registered first)."""
+    if opts is None and not kw and D.is_cuda:
+        _ensure_workspace("solve", _dtype(D), D.shape[0], 0, D.device.index)
     return _square_call("apsp_solve", D, opts, stream, kw)
+
+
+def apsp_solve_choice(device: int | None = None) -> int:
+    """Candidate index the last automatic apsp_solve ran (-1: size rule)."""
+    ch = ctypes.c_int32(-1)
+    _check(lib().apsp_solve_choice(context(device), ctypes.byref(ch)))
+    return int(ch.value)
+
+
+def apsp_features(D, stream=None) -> list[float]:
+    """The cost model's four inputs for the cost matrix D, computed on the
+    device (log2 n, log10 density, log2 batch = 0, weakly connected)."""
+    dt = _dtype(D)
+    p, ld = _matrix(D, "D")
+    n = D.shape[0]
+    _ensure_workspace("solve", dt, n, 0, D.device.index)
+    out = (ctypes.c_float * 4)()
+    _check(lib().apsp_features(context(D.device.index), dt, n, p, ld, _stream(D, stream), out))
+    return [float(v) for v in out]
 
 
 def apsp_predecessors(D, W, P=None, stream=None, method="auto"):

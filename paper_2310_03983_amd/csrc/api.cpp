@@ -80,6 +80,7 @@ struct apsp_ctx {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
+    int32_t last_choice = -1;       // candidate apsp_solve(auto) ran last (-1: size rule)
     int64_t p16_runs = 0;           // solves run with APSP_FLAG_PACKED16
     int64_t p16_redone = 0;         // ... of which were redone in int32
     uint32_t magic = 0x41505350;    // "APSP"
@@ -658,6 +659,10 @@ size_t pred_ws_bytes(int64_t n)
     return pred_layout(n).edges + align_up((size_t)m * sizeof(uint64_t));
 }
 
+// Planner feature pass of apsp_solve / apsp_features: a union-find parent
+// per vertex (counters in the context scratch).
+size_t solve_ws_bytes(int64_t n) { return kWsAlign + align_up((size_t)n * sizeof(int32_t)); }
+
 // Batched lock-step plan: [pointer record][queue order][work items].
 size_t batched_items_bound(int max_n)
 {
@@ -721,6 +726,51 @@ void fixed_plan_claim(apsp_ctx_t* ctx)
     g_fixed[ctx->device].serial = ctx->fixed_serial;
 }
 
+
+// Scratch words of the feature pass (bytes 192..207 of the context scratch).
+unsigned long long* feat_edges(apsp_ctx_t* ctx)
+{
+    return reinterpret_cast<unsigned long long*>(static_cast<char*>(ctx->d_scratch) + 192);
+}
+uint32_t* feat_roots(apsp_ctx_t* ctx) { return reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->d_scratch) + 200); }
+
+bool model_ready(const apsp_ctx_t* ctx) { return ctx->cm_params && ctx->cm_K == kNumCandidates; }
+
+// First minimum of the predicted scores among the candidates `dt` can run.
+int32_t pick_candidate(apsp_dtype_t dt, const float* pred)
+{
+    int32_t choice = -1;
+    for (int32_t i = 0; i < kNumCandidates; ++i) {
+        if (dt != APSP_I32 && (kCandidates[i].flags & APSP_FLAG_PACKED16)) continue;
+        if (choice < 0 || pred[i] < pred[choice]) choice = i;
+    }
+    return choice;
+}
+
+// Cost-model plan for one matrix, on the device: the feature pass writes
+// the four inputs next to the model's outputs, the forward pass scores every
+// candidate, and one read-back (the stream is synchronised) returns both.
+apsp_status_t plan_matrix(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ld, hipStream_t st,
+                          float* h_x, int32_t* h_choice)
+{
+    float* x = ctx->cm_io;
+    const int K = ctx->cm_K;
+    HIP_TRY(apsp::launch_graph_features((apsp::DType)dt, D, (int32_t)n, ld, reinterpret_cast<int32_t*>(ctx->ws),
+                                        feat_edges(ctx), feat_roots(ctx), x, st),
+            "feature pass");
+    HIP_TRY(apsp::launch_mlp_forward(ctx->cm_params, ctx->cm_norm, x, 1, K, ctx->cm_ws, x + 4, st), "mlp forward");
+    std::vector<float> h(4 + K);
+    HIP_TRY(hipMemcpyAsync(h.data(), x, h.size() * sizeof(float), hipMemcpyDeviceToHost, st), "plan read-back");
+    HIP_TRY(hipStreamSynchronize(st), "plan sync");
+    if (h_x) std::copy(h.begin(), h.begin() + 4, h_x);
+    *h_choice = pick_candidate(dt, h.data() + 4);
+    return APSP_OK;
+}
+
+bool opts_all_auto(const apsp_opts_t* o)
+{
+    return o->algo == APSP_ALGO_AUTO && !o->block && !o->tile && !o->closure && !o->cutover && !o->flags;
+}
 }  // namespace
 
 extern "C" {
@@ -815,7 +865,7 @@ size_t apsp_workspace_size(apsp_ctx_t* ctx, int32_t op, apsp_dtype_t dt, int64_t
         return 0;
     }
     switch (op) {
-    case APSP_OP_SOLVE: return 0;
+    case APSP_OP_SOLVE: return n_or_total > 1 ? solve_ws_bytes(n_or_total) : 0;
     case APSP_OP_BATCHED: {
         const int64_t max_n = std::min<int64_t>(n_or_total, apsp::batched_max_n());
         if (count == 0 || max_n <= 1) return batched_ws_bytes(count, 1);
@@ -964,9 +1014,21 @@ apsp_status_t apsp_solve(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, i
     case APSP_ALGO_SQUARE: return apsp_square(ctx, dt, n, D, ldd, o, stream);
     case APSP_ALGO_RKLEENE: return apsp_rkleene(ctx, dt, n, D, ldd, o, stream);
     default: {
-        // R-Kleene's top-level products are large and efficient; blocked FW
-        // has fewer launches and wins up to about n = 4096, so it also closes
-        // R-Kleene's sub-problems of that size
+        // all options automatic, a cost model for the candidate table loaded
+        // and a workspace for the feature pass: the model's pick
+        if (opts_all_auto(o) && n > 1 && model_ready(ctx) && ctx->ws && ctx->ws_bytes >= solve_ws_bytes(n)) {
+            int32_t choice = -1;
+            if ((rc = plan_matrix(ctx, dt, n, D, ldd, static_cast<hipStream_t>(stream), nullptr, &choice))) return rc;
+            ctx->ws_owner = WS_NONE;
+            apsp_opts_t po;
+            if ((rc = apsp_candidate(choice, &po))) return rc;
+            ctx->last_choice = choice;
+            return apsp_solve(ctx, dt, n, D, ldd, &po, stream);
+        }
+        ctx->last_choice = -1;
+        // size rule: R-Kleene's top-level products are large and efficient;
+        // blocked FW has fewer launches and wins up to about n = 4096, so it
+        // also closes R-Kleene's sub-problems of that size
         if (n <= 4096) return apsp_fw(ctx, dt, n, D, ldd, o, stream);
         apsp_opts_t o2 = *o;
         if (!o2.cutover) o2.cutover = 4096;
@@ -1059,6 +1121,39 @@ apsp_status_t apsp_path(apsp_ctx_t* ctx, int64_t n, const int32_t* P, int64_t ld
     HIP_TRY(apsp::launch_paths(P, ldp, (int32_t)n, count, d_src, d_dst, d_paths, max_len, d_len,
                                static_cast<hipStream_t>(stream)),
             "path launch");
+    return APSP_OK;
+}
+
+apsp_status_t apsp_features(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const void* D, int64_t ldd, void* stream,
+                            float* h_features)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
+    if (!h_features) return fail(APSP_E_ARG, "h_features is NULL");
+    if (n > INT32_MAX) return fail(APSP_E_ARG, "n too large");
+    if ((rc = check_ctx(ctx))) return rc;
+    const size_t need = n > 1 ? solve_ws_bytes(n) : 0;
+    if (need && (!ctx->ws || ctx->ws_bytes < need))
+        return fail(APSP_E_NOMEM, "apsp_features needs a workspace of %zu bytes (apsp_workspace_size)", need);
+    if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* x = reinterpret_cast<float*>(static_cast<char*>(ctx->d_scratch) + 208);
+    int32_t* parent = n > 1 ? reinterpret_cast<int32_t*>(ctx->ws) : nullptr;
+    if (n > 1) ctx->ws_owner = WS_NONE;
+    HIP_TRY(apsp::launch_graph_features((apsp::DType)dt, D, (int32_t)std::max<int64_t>(n, 0), ldd, parent,
+                                        feat_edges(ctx), feat_roots(ctx), x, st),
+            "feature pass");
+    HIP_TRY(hipMemcpyAsync(h_features, x, 4 * sizeof(float), hipMemcpyDeviceToHost, st), "feature read-back");
+    HIP_TRY(hipStreamSynchronize(st), "feature sync");
+    return APSP_OK;
+}
+
+apsp_status_t apsp_solve_choice(apsp_ctx_t* ctx, int32_t* h_choice)
+{
+    apsp_status_t rc;
+    if (!h_choice) return fail(APSP_E_ARG, "h_choice is NULL");
+    if ((rc = check_ctx(ctx))) return rc;
+    *h_choice = ctx->last_choice;
     return APSP_OK;
 }
 
@@ -1731,11 +1826,7 @@ apsp_status_t apsp_plan(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, double dens
     float pred[kNumCandidates];
     HIP_TRY(hipMemcpy(pred, ctx->cm_io + 4, sizeof pred, hipMemcpyDeviceToHost), "plan scores download");
     // first minimum among the candidates this dtype can run
-    int32_t choice = -1;
-    for (int32_t i = 0; i < kNumCandidates; ++i) {
-        if (dt != APSP_I32 && (kCandidates[i].flags & APSP_FLAG_PACKED16)) continue;
-        if (choice < 0 || pred[i] < pred[choice]) choice = i;
-    }
+    const int32_t choice = pick_candidate(dt, pred);
     if (h_choice) *h_choice = choice;
     return apsp_candidate(choice, out);
 }

@@ -149,6 +149,14 @@ hipError_t launch_paths(const int32_t* P, int64_t ldp, int32_t n, int32_t count,
 hipError_t launch_predecessors(DType dt, const void* D, int64_t ldd, const void* W, int64_t ldw, int32_t* P,
                                int64_t ldp, int32_t n, const uint32_t* skip_if_set, hipStream_t st);
 
+// ---- planner features (features.hip)
+// Edge count and weak connectivity of an n x n cost matrix: *edges (uint64)
+// and *roots (uint32, components) are zeroed first, parent (n int32) is a
+// union-find forest in the workspace; x[0..3] receives the cost model's
+// inputs (log2 n, log10 density, log2 batch = 0, connected).
+hipError_t launch_graph_features(DType dt, const void* D, int32_t n, int64_t ld, int32_t* parent,
+                                 unsigned long long* edges, uint32_t* roots, float* x, hipStream_t st);
+
 // ---- cost-model MLP (mlp.hip)
 constexpr int kMlpIn = 4;
 constexpr int kMlpHidden = 64;

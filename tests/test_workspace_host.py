@@ -21,11 +21,12 @@ L = a.lib()
 c = ctypes.c_void_p()
 assert L.apsp_create(ctypes.byref(c), 0) == 0, a.last_error()
 ws = L.apsp_workspace_size
-# operations without a workspace
-assert ws(c, 0, 0, 16384, 0) == 0
+def al(x): return (x + 255) // 256 * 256
+# solve: the planner's feature pass (one int32 union-find parent per vertex)
+assert ws(c, 0, 0, 16384, 0) == 256 + al(16384 * 4)
+assert ws(c, 0, 1, 1, 0) == 0
 # predecessors: flag, counts (ranges x n int32), offsets (+ ranges + 1, int64),
 # then up to n^2/4 edges of 8 bytes, each part 256-byte aligned
-def al(x): return (x + 255) // 256 * 256
 n = 4096; nr = 4
 want = 256 + al(nr * n * 4) + al((nr * n + nr + 1) * 8) + al(n * n // 4 * 8)
 assert ws(c, 2, 0, n, 0) == want, (ws(c, 2, 0, n, 0), want)
@@ -60,6 +61,13 @@ assert str(512) in a.last_error()
 P = ctypes.c_void_p(0x900000)
 rc = L.apsp_predecessors_ex(c, 0, 1000, fake, 1000, ctypes.c_void_p(0x500000), 1000, P, 1000, 2, None)
 assert rc == a.APSP_E_NOMEM and "workspace" in a.last_error(), (rc, a.last_error())
+# features need the workspace too
+out4 = (ctypes.c_float * 4)()
+assert L.apsp_set_workspace(c, None, 0) == 0
+assert L.apsp_features(c, 0, 100, fake, 100, None, out4) == a.APSP_E_NOMEM
+assert L.apsp_features(c, 0, 100, fake, 100, None, None) == a.APSP_E_ARG
+ch = ctypes.c_int32(5)
+assert L.apsp_solve_choice(c, ctypes.byref(ch)) == 0 and ch.value == -1
 # path queries: argument errors come first
 assert L.apsp_path(c, 10, fake, 10, -1, fake, fake, fake, 10, fake, None) == a.APSP_E_ARG
 assert L.apsp_path(c, 10, fake, 10, 1, fake, fake, fake, 0, fake, None) == a.APSP_E_ARG
