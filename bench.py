@@ -239,7 +239,9 @@ def bench_batched(torch, np, apsp, gg, dev, steps):
             apsp.apsp_batched(c, off_d, sz_d, hs, **kw)
 
     warm = 2
-    for label, kw in (("lockstep_graph_replay", {}), ("persistent_graph_replay", {"batch_persistent": True})):
+    for label, kw in (("auto_graph_replay", {}), ("lockstep_graph_replay", {"batch_lockstep": True}),
+                      ("persistent_graph_replay", {"batch_persistent": True}),
+                      ("queue_graph_replay", {"batch_queue": True})):
         copies = [flat_d.clone() for _ in range(steps + warm)]
         run_batched(copies[:warm], **kw)
         torch.cuda.synchronize()
@@ -274,7 +276,8 @@ def bench_batched(torch, np, apsp, gg, dev, steps):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     out["per_graph_solve_calls"] = {"ms_per_batch": t * 1e3, "graphs_per_s": count / t}
-    best = min(out["lockstep_graph_replay"]["ms_per_batch"], out["persistent_graph_replay"]["ms_per_batch"])
+    out["auto_choice"] = apsp.apsp_batched_choice()
+    best = out["auto_graph_replay"]["ms_per_batch"]
     out["graphs_per_s"] = count / (best / 1e3)
     out["speedup_vs_per_graph_launches"] = out["per_graph_launches"]["ms_per_batch"] / best
     out["speedup_vs_per_graph_solve"] = out["per_graph_solve_calls"]["ms_per_batch"] / best

@@ -92,6 +92,9 @@ typedef int32_t apsp_dtype_t;
 #define APSP_FLAG_BATCH_PERSISTENT 16 /* apsp_batched: one persistent kernel, one workgroup per graph */
 #define APSP_FLAG_PACKED16         32 /* int32 apsp_fw / apsp_rkleene / apsp_square / apsp_solve:
                                          min-plus products in capped 16-bit arithmetic (see below) */
+#define APSP_FLAG_BATCH_QUEUE      128 /* apsp_batched: dependency-driven schedule, one workgroup per task
+                                          (see apsp_batched) */
+#define APSP_FLAG_BATCH_LOCKSTEP   256 /* apsp_batched: the lock-step schedule (see apsp_batched) */
 #define APSP_FLAG_SKIP_INF         64 /* minplus_gemm / apsp_fw / apsp_rkleene / apsp_square / apsp_solve:
                                          a product skips every reduction slice (16 or 32 steps of one
                                          tile) whose A block or B block is all INF -- exact, since
@@ -101,7 +104,8 @@ typedef int32_t apsp_dtype_t;
 
 typedef struct apsp_opts {
     int32_t algo;      /* APSP_ALGO_*; only apsp_solve and apsp_batched read it */
-    int32_t block;     /* FW round width / R-Kleene leaf size: 0 (auto), 64 or 128 */
+    int32_t block;     /* FW round width / R-Kleene leaf size: 0 (auto), 64 or 128; apsp_batched with
+                          APSP_FLAG_BATCH_QUEUE: the round width of graphs with n > reserved[0] (others 128) */
     int32_t tile;      /* APSP_TILE_* for the min-plus products */
     int32_t closure;   /* APSP_CLOSURE_* for diagonal tiles */
     int32_t cutover;   /* R-Kleene: sub-problems <= cutover use blocked FW (0 = never) */
@@ -337,29 +341,66 @@ apsp_status_t apsp_path(apsp_ctx_t *ctx, int64_t n, const int32_t *P, int64_t ld
  * row-major matrices back to back; d_offsets[g] (int64, device) is the
  * element offset of graph g and d_sizes[g] (int32, device) its n; h_sizes is
  * the same sizes on the host (used to plan, never dereferenced on device).
- * Every matrix is overwritten with its distances (Sec. 2, Eq. 1 per graph).
- * Default schedule (lock-step): all graphs advance one 128-wide blocked-FW
- * round per launch group -- the panel tiles of every graph, then the next
- * round's pivot tiles (updated and closed) on the context's second stream
- * beside every other remainder tile -- after one launch of all round-0 pivot
- * closures; at most 3 * ceil(max n / 128) launches, captured once per batch
- * shape in a HIP graph and replayed (the buffers of each call are written to
- * a small device record first, so any buffers work); when every graph has
- * n <= 128 the schedule is the one closure launch, issued directly.
+ * Every matrix is overwritten with its distances (Sec. 2, Eq. 1 per graph,
+ * blocked into rounds).  n <= 1024 per graph (APSP_E_UNSUPPORTED beyond:
+ * use apsp_solve).
+ *
+ * Plan.  With every option automatic (opts NULL or all fields 0) the cost
+ * model picks one of the batch candidates (apsp_batch_candidate) from the
+ * batch's features (apsp_plan_batch; the density is counted on the device
+ * and read back, so the first call with a new batch shape synchronises
+ * `stream`); without a model with batch outputs the default candidate runs
+ * (the queue schedule with 64 x 64 sub-tiles for n > 128).  The plan is made
+ * once per batch shape (apsp_batched_choice reports it).  Otherwise the flags
+ * select the schedule:
+ *
+ * APSP_FLAG_BATCH_QUEUE: a dependency-driven schedule in one launch: every
+ * graph's first pivot closure, panel tiles, remainder tiles and next pivots
+ * are tasks of one workgroup each, in one ticket queue per XCD (a graph's
+ * tasks all run on one XCD, so its tiles are written and read through one
+ * L2).  Each workgroup takes the next ticket of its XCD's queue when it
+ * starts and waits, on per-graph counters in the plan memory, only for
+ * tasks with smaller tickets, so every queue drains; waits are bounded
+ * (apsp_batched_status reports an overrun).  The tickets follow a list
+ * schedule simulated on the host (longest estimated path first).  Graphs
+ * with n > opts->reserved[0] (all when 0) take round width opts->block
+ * (64 or 128; 0 = 128) and, with opts->tile = APSP_TILE_64 and 128-wide
+ * rounds, products cut into 64 x 64 sub-tile tasks; the others take 128-wide
+ * rounds of whole tiles.
+ *
+ * APSP_FLAG_BATCH_LOCKSTEP: all graphs advance one 128-wide round per launch
+ * group -- the panel tiles of every graph, then the next round's pivot tiles
+ * (updated and closed) on the context's second stream beside every other
+ * remainder tile -- after one launch of all round-0 pivot closures; at most
+ * 3 * ceil(max n / 128) launches; when every graph has n <= 128 the schedule
+ * is the one closure launch, issued directly.
+ *
  * APSP_FLAG_BATCH_PERSISTENT: one persistent kernel whose workgroups take
- * whole graphs, largest first, from an atomic queue (also graph-captured).
+ * whole graphs, largest first, from an atomic queue.
+ *
+ * The queue, lock-step and persistent launches are captured once per batch
+ * shape in a HIP graph and replayed (the buffers of each call are written to
+ * a small device record first, so any buffers work);
  * APSP_FLAG_BATCH_NO_GRAPH launches directly; APSP_FLAG_BATCH_PER_GRAPH
- * issues one launch per graph (a baseline).  n <= 1024 per graph
- * (APSP_E_UNSUPPORTED beyond: use apsp_solve).  The plan lives in the
- * workspace (apsp_workspace_size with APSP_OP_BATCHED); a workspace that is
- * missing or too small is APSP_E_NOMEM, returned before anything is
- * enqueued.  A call with a new batch shape, or after another call used the
- * workspace, uploads the plan and synchronises `stream`; calls on one
- * context must not overlap across streams.
+ * issues one launch of the persistent kernel per graph (a baseline).  The
+ * plan lives in the workspace (apsp_workspace_size with APSP_OP_BATCHED); a
+ * workspace that is missing or too small is APSP_E_NOMEM, returned before
+ * anything is enqueued.  A call with a new batch shape, or after another
+ * call used the workspace, uploads the plan and synchronises `stream`; calls
+ * on one context must not overlap across streams.
  */
 apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
                            void *data, const int64_t *d_offsets, const int32_t *d_sizes,
                            const int32_t *h_sizes, const apsp_opts_t *opts, void *stream);
+
+/*
+ * Diagnostic of the APSP_FLAG_BATCH_QUEUE schedule: *h_flags receives the
+ * error word of the last batched plan (bit 0: a dependency wait overran its
+ * bounded poll count since the last call, so that launch's results are not
+ * guaranteed) and the word is cleared.  Synchronises `stream`.  0 when no
+ * batched plan is resident.
+ */
+apsp_status_t apsp_batched_status(apsp_ctx_t *ctx, void *stream, uint32_t *h_flags);
 
 /*
  * apsp_batched for callers that cannot allocate device memory or register a
@@ -401,10 +442,12 @@ apsp_status_t apsp_candidate(int32_t index, apsp_opts_t *out);
 /*
  * Cost model: a small MLP, 4 features -> 64 -> 64 -> K (ReLU hidden layers),
  * whose K outputs are predicted normalised log run times of the K candidate
- * plans; the plan is the argmin.  Features of a problem, in this order:
+ * plans; the plan is the argmin.  Features of one graph, in this order:
  *   log2(n), log10(density) with density = edges / (n (n-1)) (clamped to
- *   1e-9), log2(graphs in the batch), 1 if the graph is weakly connected
- *   else 0.
+ *   1e-9), 0 (log2 of a batch of one), 1 if the graph is weakly connected
+ *   else 0; of a batch: see apsp_plan_batch.  A model that plans both has
+ *   apsp_candidate_count() + apsp_batch_candidate_count() outputs, the
+ *   single-graph candidates first.
  * Parameters are one fp32 array, row-major input x output:
  *   W1[4][64] | b1[64] | W2[64][64] | b2[64] | W3[64][K] | b3[K]
  * (4480 + 65 K floats).  Inputs are standardised inside the kernels with the
@@ -454,13 +497,40 @@ apsp_status_t apsp_costmodel_forward(apsp_ctx_t *ctx, const float *d_X, int32_t 
 apsp_status_t apsp_costmodel_predict(apsp_ctx_t *ctx, const float *d_X, int32_t rows, int32_t *d_choice,
                                      void *stream);
 
-/* Plan for one problem of `dtype` (synchronous): the cost model's argmin
- * over the candidates that dtype can run (fp32 skips the APSP_FLAG_PACKED16
- * ones) when a model with K = apsp_candidate_count() is loaded, else a size
- * rule (blocked FW up to n = 4096, R-Kleene with a 4096 FW cutover above).
- * *h_choice (may be NULL) gets the candidate index, or -1 for the size rule. */
+/* Plan for one graph of `dtype` (synchronous; batch must be 1): the cost
+ * model's argmin over the candidates that dtype can run (fp32 skips the
+ * APSP_FLAG_PACKED16 ones) when a model with at least apsp_candidate_count()
+ * outputs is loaded, else a size rule (blocked FW up to n = 4096, R-Kleene
+ * with a 4096 FW cutover above).  *h_choice (may be NULL) gets the candidate
+ * index, or -1 for the size rule. */
 apsp_status_t apsp_plan(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n, double density, int32_t batch,
                         int32_t connected, apsp_opts_t *out, int32_t *h_choice);
+
+/*
+ * Batch candidate plans of apsp_batched (schedule flags, round width, tile,
+ * reserved[0] = the n above which a graph takes that width and tile), indexed
+ * 0 .. apsp_batch_candidate_count() - 1: lock-step; queue with whole
+ * 128-tiles; queue with 64 x 64 sub-tiles for n > 128; for n > 256; queue
+ * with 64-wide rounds for n > 384; persistent.
+ */
+int32_t apsp_batch_candidate_count(void);
+apsp_status_t apsp_batch_candidate(int32_t index, apsp_opts_t *out);
+
+/*
+ * Plan for a batch (synchronous): when the loaded model has
+ * apsp_candidate_count() + apsp_batch_candidate_count() outputs (the batch
+ * candidates last), the argmin of its batch outputs for the features
+ * log2(largest n), log10(density) with density = edges / sum n (n-1) over
+ * the batch (clamped to 1e-9), log2(count), and the share of the batch's
+ * work (sum of n^3) in graphs with n > 256; else the default candidate.
+ * *h_choice (may be NULL) gets the batch candidate index, or -1 for the
+ * default.
+ */
+apsp_status_t apsp_plan_batch(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count, const int32_t *h_sizes,
+                              double density, apsp_opts_t *out, int32_t *h_choice);
+
+/* Batch candidate the last automatic apsp_batched plan chose (-1: none yet). */
+apsp_status_t apsp_batched_choice(apsp_ctx_t *ctx, int32_t *h_choice);
 
 /*
  * Kernel timing for measurement tools (not needed to compute anything).

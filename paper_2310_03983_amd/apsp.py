@@ -26,6 +26,8 @@ TILE = {"auto": 0, 128: 1, 64: 2}
 FLAG_NO_SPLITK, FLAG_BATCH_NO_GRAPH, FLAG_BATCH_PER_GRAPH, FLAG_NO_LOOKAHEAD, FLAG_BATCH_PERSISTENT = 1, 2, 4, 8, 16
 FLAG_PACKED16 = 32
 FLAG_SKIP_INF = 64
+FLAG_BATCH_QUEUE = 128
+FLAG_BATCH_LOCKSTEP = 256
 CAP16 = 0x39FF    # 14847: cap of the APSP_FLAG_PACKED16 products
 
 # every symbol include/apsp.h declares
@@ -39,7 +41,8 @@ EXPORTS = [
     "apsp_costmodel_forward", "apsp_costmodel_predict", "apsp_plan", "apsp_predecessors",
     "apsp_packed16_counts", "apsp_predecessors_ex", "apsp_measure_fold_rate",
     "apsp_workspace_size", "apsp_set_workspace", "apsp_path", "apsp_batched_noalloc",
-    "apsp_features", "apsp_solve_choice",
+    "apsp_features", "apsp_solve_choice", "apsp_batched_status",
+    "apsp_batch_candidate_count", "apsp_batch_candidate", "apsp_plan_batch", "apsp_batched_choice",
 ]
 # the trained cost model shipped with the package (plain-text model file)
 MODEL_PATH = os.path.join(_PKG, "data", "costmodel_mlp.txt")
@@ -75,7 +78,7 @@ class KernelStats(ctypes.Structure):
 
 def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True,
               batch_graph=True, batch_per_graph=False, lookahead=True, batch_persistent=False,
-              packed16=False, skip_inf=False) -> Opts:
+              packed16=False, skip_inf=False, batch_queue=False, batch_lockstep=False) -> Opts:
     o = Opts()
     o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
     o.block = int(block)
@@ -85,7 +88,8 @@ def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, spli
     o.flags = (0 if splitk else FLAG_NO_SPLITK) | (0 if batch_graph else FLAG_BATCH_NO_GRAPH) | \
         (FLAG_BATCH_PER_GRAPH if batch_per_graph else 0) | (0 if lookahead else FLAG_NO_LOOKAHEAD) | \
         (FLAG_BATCH_PERSISTENT if batch_persistent else 0) | (FLAG_PACKED16 if packed16 else 0) | \
-        (FLAG_SKIP_INF if skip_inf else 0)
+        (FLAG_SKIP_INF if skip_inf else 0) | (FLAG_BATCH_QUEUE if batch_queue else 0) | \
+        (FLAG_BATCH_LOCKSTEP if batch_lockstep else 0)
     return o
 
 
@@ -142,6 +146,11 @@ def lib() -> ctypes.CDLL:
             L.apsp_path.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, i32, vp, vp]
             L.apsp_features.argtypes = [vp, i32, i64, vp, i64, vp, P(ctypes.c_float)]
             L.apsp_solve_choice.argtypes = [vp, P(i32)]
+            L.apsp_batched_status.argtypes = [vp, vp, P(ctypes.c_uint32)]
+            L.apsp_batch_candidate_count.argtypes = []
+            L.apsp_batch_candidate.argtypes = [i32, P(Opts)]
+            L.apsp_plan_batch.argtypes = [vp, i32, i32, P(i32), ctypes.c_double, P(Opts), P(i32)]
+            L.apsp_batched_choice.argtypes = [vp, P(i32)]
             for name in EXPORTS:
                 if name not in ("apsp_last_error", "apsp_version", "apsp_workspace_size"):
                     getattr(L, name).restype = i32
@@ -417,6 +426,16 @@ def apsp_batched_noalloc(data: torch.Tensor, offsets: torch.Tensor, sizes: torch
     return data
 
 
+def apsp_batched_status(device: int | None = None) -> int:
+    """Error word of the last batched plan (bit 0: a queue wait overran),
+    cleared by the call."""
+    dev = torch.cuda.current_device() if device is None else device
+    f = ctypes.c_uint32(0)
+    _check(lib().apsp_batched_status(context(dev), ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream),
+                                     ctypes.byref(f)))
+    return int(f.value)
+
+
 def apsp_profile_enable(on: bool = True, kinds=None, device: int | None = None):
     """Starts (clearing old records) or stops per-launch event timing; with
     `kinds` (iterable of KERNEL_*) only those kernels are bracketed."""
@@ -459,6 +478,34 @@ def apsp_candidate(index: int) -> Opts:
     o = Opts()
     _check(lib().apsp_candidate(index, ctypes.byref(o)))
     return o
+
+
+def apsp_batch_candidate_count() -> int:
+    return int(lib().apsp_batch_candidate_count())
+
+
+def apsp_batch_candidate(index: int) -> Opts:
+    o = Opts()
+    _check(lib().apsp_batch_candidate(index, ctypes.byref(o)))
+    return o
+
+
+def apsp_plan_batch(h_sizes, density: float, dtype: str = "int32", device: int | None = None):
+    """(Opts, batch candidate index or -1 for the default) for a batch of the
+    given sizes and density (apsp_plan_batch)."""
+    o = Opts()
+    ch = ctypes.c_int32(-1)
+    hs = (ctypes.c_int32 * max(len(h_sizes), 1))(*[int(x) for x in h_sizes])
+    _check(lib().apsp_plan_batch(context(device), {"int32": 0, "float32": 1}[dtype], len(h_sizes), hs,
+                                 float(density), ctypes.byref(o), ctypes.byref(ch)))
+    return o, int(ch.value)
+
+
+def apsp_batched_choice(device: int | None = None) -> int:
+    """Batch candidate the last automatic apsp_batched plan chose (-1: none)."""
+    ch = ctypes.c_int32(-1)
+    _check(lib().apsp_batched_choice(context(device), ctypes.byref(ch)))
+    return int(ch.value)
 
 
 def mlp_param_count(K: int) -> int:

@@ -4,6 +4,8 @@
     python -m paper_2310_03983_amd.autotune train --db timings.json --model model.json
     python -m paper_2310_03983_amd.autotune evaluate --db timings.json --model model.json
     python -m paper_2310_03983_amd.autotune batch --db batch_timings.json
+    python -m paper_2310_03983_amd.autotune train-joint --db timings.json --batch-db batch_timings.json --model m.json
+    python -m paper_2310_03983_amd.autotune evaluate-joint --db timings.json --batch-db batch_timings.json --model m.json
     python -m paper_2310_03983_amd.autotune export --model model.json --out model.txt
 
 `sweep` times every candidate plan of the library (apsp_candidate) on every
@@ -21,10 +23,13 @@ argmin is unchanged).  `evaluate` reports, on held-out graphs, the regret
 t(pick)/t(best) - 1 of the model's pick against exhaustive tuning, next to
 the best single static candidate and the library's size rule.
 
-`batch` times every schedule of apsp_batched (lock-step graph replay,
-lock-step direct launches, persistent kernel, one launch per graph) on the
-512-graph ragged batch and on each size class of it, checks that they agree,
-and writes the winner per class.
+`batch` times every batch candidate of apsp_batched (lock-step, the queue
+schedule with whole tiles, sub-tiles above n = 128 or 256, 64-wide rounds
+above n = 384, the persistent kernel) on the 160 batches of the batch sweep
+(graph count, size range and density varied), checks that they agree, and
+stores the medians; `train-joint` fits one model whose outputs score the
+single-graph candidates and the batch candidates (masked targets), and
+`evaluate-joint` reports both regrets on held-out graphs and batches.
 `export` writes a trained model in the text format of apsp_costmodel_load.
 At run time `choose` plans one graph: the installed model's pick, or
 exhaustive tuning of that graph when no matching model is installed.
@@ -182,57 +187,98 @@ def sweep(db_path, first=0, last=199, progress=print):
 
 
 # ---------------------------------------------------------------------------
-# batched schedules, per size class
+# batched plans
 # ---------------------------------------------------------------------------
 
-BATCH_SCHEDULES = {
-    "lockstep": {},
-    "lockstep_direct": {"batch_graph": False},
-    "persistent": {"batch_persistent": True},
-    "per_graph": {"batch_persistent": True, "batch_per_graph": True},
-}
-SIZE_CLASSES = [(32, 64), (64, 128), (128, 256), (256, 513)]
+# batches the joint model trains on, and the held-out ones it is scored on
+BATCH_TRAIN = list(range(120)) + list(range(160, 200))
+BATCH_TEST = list(range(120, 160))
 
 
-def sweep_batch(reps=10, progress=print):
-    """Times every batched schedule of apsp_batched on the 512-graph ragged
-    batch and on its size classes (graphs with n in [lo, hi)), each class
-    packed as a batch of its own; checks that all schedules give the same
-    distances; returns {class: {schedule: ms, "best": name}}."""
+def batch_candidate_table(apsp):
+    out = []
+    for i in range(apsp.apsp_batch_candidate_count()):
+        o = apsp.apsp_batch_candidate(i)
+        out.append({"flags": o.flags, "block": o.block, "tile": o.tile, "split": o.reserved[0]})
+    return out
+
+
+def batch_features(mats) -> list[float]:
+    """The batch planner's inputs (as apsp_plan_batch computes them): log2
+    of the largest n, log10 density over the batch, log2 of the count, and
+    the share of the work (sum of n^3) in graphs with n > 256."""
+    ns = np.array([m.shape[0] for m in mats], dtype=np.float64)
+    edges = sum(int(np.count_nonzero(m < gg.INF_I32)) - m.shape[0] for m in mats)
+    pairs = float((ns * np.maximum(ns - 1, 0)).sum())
+    w = ns ** 3
+    dens = edges / pairs if pairs > 0 else 0.0
+    return [math.log2(max(ns.max(), 1)), math.log10(max(dens, 1e-9)), math.log2(max(len(mats), 1)),
+            float(w[ns > 256].sum() / w.sum()) if w.sum() > 0 else 0.0]
+
+
+def time_batch(torch, apsp, flat_d, off_d, sz_d, hs, opts, reps):
+    """Median milliseconds of apsp_batched(opts) (HIP events around each
+    call; the input restored before every call) and the last result."""
+    work = flat_d.clone()
+    apsp.apsp_batched(work, off_d, sz_d, hs, opts=opts)   # plan, capture
+    ts = []
+    for _ in range(reps):
+        work.copy_(flat_d)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        apsp.apsp_batched(work, off_d, sz_d, hs, opts=opts)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), work
+
+
+def sweep_batches(db_path, first=0, last=199, reps=7, progress=print):
+    """Times every batch candidate of apsp_batched on the batch sweep
+    (graphgen.batch_sweep) and appends the medians to a JSON database
+    (resumable); every candidate's distances are compared bit for bit with
+    the first candidate's."""
     import torch
     from . import apsp
     dev = torch.device("cuda:0")
-    batch = gg.batch_ragged()
-    mats = [gg.batch_graph_i32(b) for b in batch]
-    classes = [("all", 0, 1 << 30)] + [(f"n{lo}-{hi - 1}", lo, hi) for lo, hi in SIZE_CLASSES]
-    out = {}
-    for name, lo, hi in classes:
-        sel = [m for m in mats if lo <= m.shape[0] < hi]
-        flat, off, sz = gg.pack_batch(sel)
+    db = load_db(db_path)
+    cands = batch_candidate_table(apsp)
+    if db.get("candidates") not in (None, cands):
+        db = {"version": DB_VERSION, "records": {}}
+    db["candidates"] = cands
+    db["device"] = torch.cuda.get_device_name(0)
+    for spec in gg.batch_sweep()[first:last + 1]:
+        key = str(spec.b)
+        if key in db["records"]:
+            continue
+        t0 = time.time()
+        mats = [gg.batch_graph_i32(g) for g in spec.graphs()]
+        feats = batch_features(mats)
+        flat, off, sz = gg.pack_batch(mats)
+        del mats
         flat_d = torch.from_numpy(flat).to(dev)
         off_d, sz_d = torch.from_numpy(off).to(dev), torch.from_numpy(sz).to(dev)
         hs = sz.tolist()
-        rec, ref = {"graphs": len(sel)}, None
-        for sched, kw in BATCH_SCHEDULES.items():
-            r = max(2, reps // 5) if sched == "per_graph" else reps
-            copies = [flat_d.clone() for _ in range(r + 1)]
-            apsp.apsp_batched(copies[0], off_d, sz_d, hs, **kw)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for c in copies[1:]:
-                apsp.apsp_batched(c, off_d, sz_d, hs, **kw)
-            torch.cuda.synchronize()
-            rec[sched] = (time.perf_counter() - t0) / r * 1e3
+        times, agree, ref = [], True, None
+        for i in range(len(cands)):
+            ms, out = time_batch(torch, apsp, flat_d, off_d, sz_d, hs, apsp.apsp_batch_candidate(i), reps)
+            times.append(ms)
             if ref is None:
-                ref = copies[-1]
-            elif not torch.equal(ref, copies[-1]):
-                raise RuntimeError(f"schedule {sched} disagrees on class {name}")
-            del copies
-        rec["best"] = min(BATCH_SCHEDULES, key=lambda k: rec[k])
-        out[name] = rec
-        progress(f"[autotune] batch class {name}: {len(sel)} graphs, best {rec['best']} "
-                 + " ".join(f"{k}={rec[k]:.3f}ms" for k in BATCH_SCHEDULES))
-    return out
+                ref = out
+            else:
+                agree = agree and bool(torch.equal(ref, out))
+            if apsp.apsp_batched_status() != 0:
+                agree = False
+        db["records"][key] = {"b": spec.b, "count": spec.count, "n_lo": spec.n_lo, "n_hi": spec.n_hi,
+                              "p_hi": spec.p_hi, "features": feats, "times": times, "agree": agree}
+        save_db(db, db_path)
+        best = int(np.argmin(times))
+        progress(f"[autotune] batch {spec.b}: {spec.count} graphs n {spec.n_lo}-{spec.n_hi} best={best} "
+                 f"({' '.join(f'{t:.3f}' for t in times)} ms) agree={agree} ({time.time() - t0:.1f} s)")
+        del flat_d, ref
+        torch.cuda.empty_cache()
+    return db
 
 
 # ---------------------------------------------------------------------------
@@ -244,6 +290,85 @@ def dataset(db, ids):
     X = np.array([r["features"] for r in recs], dtype=np.float32)
     L = np.log(np.array([r["times"] for r in recs], dtype=np.float64))
     return recs, X, L
+
+
+def train_joint(db, ids, bdb, bids, steps=4000, lr=3e-3, seed=0):
+    """One model for both planners: K = single candidates + batch
+    candidates outputs; single-graph rows carry targets for the first ones
+    (mask 1) and none for the batch outputs (mask 0), batch rows the other
+    way round.  Log times standardised with one mean/deviation over every
+    target present (so each row's argmin is unchanged)."""
+    import torch
+    from . import apsp
+    dev = torch.device("cuda:0")
+    _, Xs, Ls = dataset(db, ids)
+    brecs = [bdb["records"][str(b)] for b in bids if str(b) in bdb["records"]]
+    Xb = np.array([r["features"] for r in brecs], dtype=np.float32)
+    Lb = np.log(np.array([r["times"] for r in brecs], dtype=np.float64))
+    Ks, Kb = Ls.shape[1], Lb.shape[1]
+    K = Ks + Kb
+    X = np.concatenate([Xs, Xb]).astype(np.float32)
+    L = np.zeros((X.shape[0], K))
+    M = np.zeros((X.shape[0], K), dtype=np.float32)
+    L[:len(Xs), :Ks], M[:len(Xs), :Ks] = Ls, 1.0
+    L[len(Xs):, Ks:], M[len(Xs):, Ks:] = Lb, 1.0
+    mu = X.mean(axis=0)
+    sd = X.std(axis=0)
+    sd[sd < 1e-6] = 1.0
+    present = M > 0
+    lmu, lsd = float(L[present].mean()), float(L[present].std() or 1.0)
+    T = np.where(present, (L - lmu) / lsd, 0.0).astype(np.float32)
+    apsp.apsp_costmodel_init(K, seed)
+    apsp.apsp_costmodel_set_norm(mu, sd)
+    losses = torch.empty(steps, dtype=torch.float32, device=dev)
+    apsp.apsp_costmodel_train(torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev),
+                              torch.from_numpy(M).to(dev), steps=steps, lr=lr, losses=losses)
+    torch.cuda.synchronize()
+    h = losses.cpu().numpy()
+    return {"version": DB_VERSION, "K": K, "K_single": Ks, "K_batch": Kb, "mu": mu.tolist(), "sd": sd.tolist(),
+            "log_mu": lmu, "log_sd": lsd, "params": apsp.apsp_costmodel_get_params(K).tolist(),
+            "candidates": db["candidates"], "batch_candidates": bdb["candidates"], "train_ids": list(ids),
+            "batch_train_ids": list(bids), "steps": steps, "lr": lr, "seed": seed,
+            "loss_first": float(h[0]), "loss_last": float(h[-1])}
+
+
+def forward(model, X):
+    """The installed model's outputs for the rows of X (device forward pass)."""
+    import torch
+    from . import apsp
+    install(model)
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+    out = torch.empty((X.shape[0], model["K"]), dtype=torch.float32, device=dev)
+    apsp.apsp_costmodel_forward(Xd, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def evaluate_batches(bdb, model, test_ids, train_ids):
+    """Regret on held-out batches of the model's batch pick against
+    exhaustive tuning, next to the best static batch candidate, the former
+    fixed plan (lock-step, candidate 0) and the library's default candidate."""
+    recs = [bdb["records"][str(b)] for b in test_ids if str(b) in bdb["records"]]
+    tr = [bdb["records"][str(b)] for b in train_ids if str(b) in bdb["records"]]
+    X = np.array([r["features"] for r in recs], dtype=np.float32)
+    T = np.array([r["times"] for r in recs], dtype=np.float64)
+    Ks = model["K_single"]
+    pick = np.argmin(forward(model, X)[:, Ks:], axis=1)
+    best = T.min(axis=1)
+    Ttr = np.array([r["times"] for r in tr], dtype=np.float64)
+    static = int(np.argmin(np.exp(np.log(Ttr / Ttr.min(axis=1, keepdims=True)).mean(axis=0))))
+
+    def stats(choice):
+        t = T[np.arange(len(T)), choice]
+        reg = t / best - 1.0
+        return {"mean_regret": float(reg.mean()), "max_regret": float(reg.max()),
+                "geomean_ratio": float(np.exp(np.log1p(reg).mean())), "total_ms": float(t.sum()),
+                "exact_picks": int((reg == 0).sum())}
+
+    return {"batches": len(recs), "mlp": stats(pick), "static_best": {"candidate": static, **stats(
+        np.full(len(T), static))}, "lockstep": stats(np.zeros(len(T), dtype=int)),
+        "default": stats(np.full(len(T), 2)), "exhaustive_total_ms": float(best.sum())}
 
 
 def train(db, ids, steps=3000, lr=3e-3, seed=0):
@@ -346,7 +471,7 @@ def evaluate(db, model, test_ids, train_ids):
     recs, X, L = dataset(db, test_ids)
     T = np.exp(L)
     best = T.min(axis=1)
-    pick = predict(model, X)
+    pick = np.argmin(forward(model, X)[:, :L.shape[1]], axis=1)
     # best single static choice on the training graphs (geometric mean of t / t_best)
     tr_ratio = np.exp(Ltr - Ltr.min(axis=1, keepdims=True))
     static = int(np.argmin(np.exp(np.log(tr_ratio).mean(axis=0))))
@@ -366,7 +491,10 @@ def evaluate(db, model, test_ids, train_ids):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["sweep", "train", "evaluate", "batch", "export"])
+    ap.add_argument("cmd", choices=["sweep", "train", "evaluate", "batch", "export", "train-joint",
+                                    "evaluate-joint"])
+    ap.add_argument("--batch-db", help="batch timing database (batch, train-joint, evaluate-joint)")
+
     ap.add_argument("--out", help="export: path of the text model file")
     ap.add_argument("--db")
     ap.add_argument("--model")
@@ -385,15 +513,25 @@ def main(argv=None):
         sweep(a.db, a.first, a.last, progress=lambda m: print(m, flush=True))
         return 0
     if a.cmd == "batch":
-        import torch
-        res = sweep_batch(progress=lambda m: print(m, flush=True))
-        with open(a.db, "w") as f:
-            json.dump({"device": torch.cuda.get_device_name(0), "schedules": BATCH_SCHEDULES, "classes": res}, f,
-                      indent=1)
+        sweep_batches(a.db, a.first, a.last, progress=lambda m: print(m, flush=True))
         return 0
     db = load_db(a.db)
     train_ids = list(range(a.train_count))
     test_ids = list(range(a.train_count, 200))
+    if a.cmd in ("train-joint", "evaluate-joint"):
+        bdb = load_db(a.batch_db)
+        btrain, btest = BATCH_TRAIN, BATCH_TEST
+        if a.cmd == "train-joint":
+            model = train_joint(db, train_ids, bdb, btrain, steps=a.steps)
+            with open(a.model, "w") as f:
+                json.dump(model, f)
+            print(json.dumps({k: model[k] for k in ("K", "loss_first", "loss_last", "steps")}))
+            return 0
+        with open(a.model) as f:
+            model = json.load(f)
+        print(json.dumps({"single": evaluate(db, model, test_ids, train_ids),
+                          "batch": evaluate_batches(bdb, model, btest, btrain)}, indent=1))
+        return 0
     if a.cmd == "train":
         model = train(db, train_ids, steps=a.steps)
         with open(a.model, "w") as f:

@@ -63,8 +63,15 @@ struct apsp_ctx {
     struct Launch { int phase, offset, count; bool side; };   // side: on the second stream
     std::vector<Launch> llaunches;
     uint64_t graph_key = 0;         // plan key the captured graphs were made for
+    uint32_t* batch_err = nullptr;  // error word of the queue schedule's last plan memory
     hipGraph_t lgraph = nullptr;
     hipGraphExec_t lexec = nullptr;
+    // dependency-driven batched schedule: tasks, counter count, captured graph
+    std::vector<apsp::BatchTask> qtasks;
+    std::vector<int32_t> qoff;      // queue x: tasks qoff[x] .. qoff[x+1] (one queue per XCD)
+    int32_t qcounters = 0;
+    hipGraph_t qgraph = nullptr;
+    hipGraphExec_t qexec = nullptr;
     // cost model
     int32_t cm_K = 0;
     float* cm_params = nullptr;     // device: parameters, Adam moments, gradients
@@ -81,6 +88,8 @@ struct apsp_ctx {
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     int32_t last_choice = -1;       // candidate apsp_solve(auto) ran last (-1: size rule)
+    uint64_t bauto_key = 0;         // batch shape the automatic batched plan was made for
+    int32_t bauto_choice = -1;      // its batch candidate
     int64_t p16_runs = 0;           // solves run with APSP_FLAG_PACKED16
     int64_t p16_redone = 0;         // ... of which were redone in int32
     uint32_t magic = 0x41505350;    // "APSP"
@@ -597,6 +606,33 @@ const Candidate kCandidates[] = {
     {APSP_ALGO_SQUARE, 0, APSP_TILE_AUTO, APSP_CLOSURE_AUTO, 0, APSP_FLAG_PACKED16},
 };
 constexpr int32_t kNumCandidates = (int32_t)(sizeof(kCandidates) / sizeof(kCandidates[0]));
+
+// Candidate plans of apsp_batched (scored by the cost model's last outputs):
+// schedule flags, round width of the large graphs, sub-tiled products
+// (tile = APSP_TILE_64), and the n above which a graph counts as large.
+struct BatchCandidate {
+    int32_t flags, block, tile, split;
+};
+const BatchCandidate kBatchCandidates[] = {
+    {APSP_FLAG_BATCH_LOCKSTEP, 0, 0, 0},                    // lock-step, 128-wide rounds
+    {APSP_FLAG_BATCH_QUEUE, 128, 0, 0},                     // queue, whole 128-tiles
+    {APSP_FLAG_BATCH_QUEUE, 128, APSP_TILE_64, 128},        // queue, 64 x 64 sub-tiles for n > 128
+    {APSP_FLAG_BATCH_QUEUE, 128, APSP_TILE_64, 256},        // queue, 64 x 64 sub-tiles for n > 256
+    {APSP_FLAG_BATCH_QUEUE, 64, 0, 384},                    // queue, 64-wide rounds for n > 384
+    {APSP_FLAG_BATCH_PERSISTENT, 0, 0, 0},                  // persistent, one workgroup per graph
+};
+constexpr int32_t kNumBatchCandidates = (int32_t)(sizeof(kBatchCandidates) / sizeof(kBatchCandidates[0]));
+constexpr int32_t kDefaultBatchCandidate = 2;   // without a cost model
+
+void batch_candidate_opts(int32_t i, apsp_opts_t* out)
+{
+    *out = apsp_opts_t{};
+    const BatchCandidate& c = kBatchCandidates[i];
+    out->flags = c.flags;
+    out->block = c.block;
+    out->tile = c.tile;
+    out->reserved[0] = c.split;
+}
 constexpr int32_t kCmMaxRows = 4096;
 
 uint64_t mix64(uint64_t z)
@@ -663,17 +699,63 @@ size_t pred_ws_bytes(int64_t n)
 // per vertex (counters in the context scratch).
 size_t solve_ws_bytes(int64_t n) { return kWsAlign + align_up((size_t)n * sizeof(int32_t)); }
 
-// Batched lock-step plan: [pointer record][queue order][work items].
-size_t batched_items_bound(int max_n)
+// Batched plan: [pointer record][ticket, error word][queue order]
+// [lock-step items][queue tasks][queue counters], each part 256-aligned.
+struct BatchLayout {
+    size_t ticket, err, qoff, order, items, tasks, counters, bytes;
+};
+constexpr int kMaxXcds = 8;
+BatchLayout batch_layout(int32_t count, size_t items, size_t tasks, int32_t counters)
+{
+    BatchLayout L;
+    L.ticket = kWsAlign;                                   // one 256-byte slot per XCD queue
+    L.err = L.ticket + kMaxXcds * kWsAlign;
+    L.qoff = L.err + kWsAlign;
+    L.order = L.qoff + kWsAlign;
+    L.items = L.order + align_up((size_t)count * sizeof(int32_t));
+    L.tasks = L.items + align_up(items * sizeof(int4));
+    L.counters = L.tasks + align_up(tasks * sizeof(apsp::BatchTask));
+    L.bytes = L.counters + align_up((size_t)std::max(counters, 1) * sizeof(int32_t));
+    return L;
+}
+// XCDs of the device: MI355X has 8 XCDs of 32 CUs (a partitioned device
+// exposes fewer CUs and so fewer XCDs).
+int num_xcds(const apsp_ctx_t* ctx) { return std::max(1, std::min(kMaxXcds, ctx->num_cus / 32)); }
+
+// Per-graph plan of the queue schedule: graphs with n > opts->reserved[0]
+// (every graph when it is 0) take round width opts->block (0: 128) and, with
+// opts->tile = APSP_TILE_64, products cut into 64 x 64 sub-tile tasks; the
+// others take 128-wide rounds of whole tiles.
+int queue_width(const apsp_opts_t* o, int n)
+{
+    const int wide = o->block ? o->block : 128;
+    return n > o->reserved[0] ? wide : 128;
+}
+int queue_sub(const apsp_opts_t* o, int n)
+{
+    return (n > o->reserved[0] && o->tile == APSP_TILE_64 && queue_width(o, n) == 128) ? 64 : 0;
+}
+
+// Upper bounds per graph of n <= max_n (nb 128-wide rounds): lock-step
+// items, queue tasks, queue counters.
+int64_t batched_rounds(int max_n)
 {
     const int64_t B = apsp::batched_round_width();
-    const int64_t nb = (max_n + B - 1) / B;
+    return (max_n + B - 1) / B;
+}
+size_t batched_items_bound(int max_n)
+{
+    const int64_t nb = batched_rounds(max_n);
     return (size_t)(1 + nb * (2 * (nb - 1) + 1 + 4 * nb * nb));
 }
-size_t batched_ws_bytes(int32_t count, size_t items)
+// queue tasks and counters: bounded by the narrowest round width (64)
+int64_t queue_rounds_bound(int max_n) { return (max_n + 63) / 64; }
+size_t batched_tasks_bound(int max_n)
 {
-    return kWsAlign + align_up((size_t)count * sizeof(int32_t)) + align_up(std::max<size_t>(items, 1) * sizeof(int4));
+    const int64_t nb = queue_rounds_bound(max_n);
+    return (size_t)(1 + nb * (2 * (nb - 1) + 1 + nb * nb));
 }
+
 // Drops the captured batched launches (after the stream has drained them).
 void drop_batch_graphs(apsp_ctx_t* ctx)
 {
@@ -686,6 +768,10 @@ void drop_batch_graphs(apsp_ctx_t* ctx)
     ctx->bnode = nullptr;
     ctx->lexec = nullptr;
     ctx->lgraph = nullptr;
+    if (ctx->qexec) hipGraphExecDestroy(ctx->qexec);
+    if (ctx->qgraph) hipGraphDestroy(ctx->qgraph);
+    ctx->qexec = nullptr;
+    ctx->qgraph = nullptr;
 }
 
 // Device addresses of the fixed scratch, one per GPU, and the serial of the
@@ -734,7 +820,13 @@ unsigned long long* feat_edges(apsp_ctx_t* ctx)
 }
 uint32_t* feat_roots(apsp_ctx_t* ctx) { return reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->d_scratch) + 200); }
 
-bool model_ready(const apsp_ctx_t* ctx) { return ctx->cm_params && ctx->cm_K == kNumCandidates; }
+// A model scores the single-graph candidates when it has at least their K
+// outputs, and the batch candidates when it has both sets (batch outputs last).
+bool model_ready(const apsp_ctx_t* ctx) { return ctx->cm_params && ctx->cm_K >= kNumCandidates; }
+bool batch_model_ready(const apsp_ctx_t* ctx)
+{
+    return ctx->cm_params && ctx->cm_K == kNumCandidates + kNumBatchCandidates;
+}
 
 // First minimum of the predicted scores among the candidates `dt` can run.
 int32_t pick_candidate(apsp_dtype_t dt, const float* pred)
@@ -868,8 +960,11 @@ size_t apsp_workspace_size(apsp_ctx_t* ctx, int32_t op, apsp_dtype_t dt, int64_t
     case APSP_OP_SOLVE: return n_or_total > 1 ? solve_ws_bytes(n_or_total) : 0;
     case APSP_OP_BATCHED: {
         const int64_t max_n = std::min<int64_t>(n_or_total, apsp::batched_max_n());
-        if (count == 0 || max_n <= 1) return batched_ws_bytes(count, 1);
-        return batched_ws_bytes(count, (size_t)count * batched_items_bound((int)max_n));
+        const int32_t nb = (int32_t)queue_rounds_bound((int)std::max<int64_t>(max_n, 1));
+        return batch_layout(count, (size_t)count * batched_items_bound((int)std::max<int64_t>(max_n, 1)),
+                            (size_t)count * batched_tasks_bound((int)std::max<int64_t>(max_n, 1)),
+                            count * (nb >= 2 ? 4 * nb : 0) + kMaxXcds * (int32_t)(kWsAlign / sizeof(int32_t)))
+            .bytes;
     }
     case APSP_OP_PREDECESSORS:
         if (n_or_total <= 1 || n_or_total > kPredSparseMaxN) return 0;
@@ -890,10 +985,12 @@ apsp_status_t apsp_set_workspace(apsp_ctx_t* ctx, void* d_ptr, size_t bytes)
     if (d_ptr == ctx->ws && bytes == ctx->ws_bytes) return APSP_OK;
     // captured batched launches point into the old workspace: let any that
     // are still running finish before they are destroyed
-    if (ctx->bexec || ctx->lexec) HIP_TRY(hipDeviceSynchronize(), "workspace change sync");
+    if (ctx->bexec || ctx->lexec || ctx->qexec) HIP_TRY(hipDeviceSynchronize(), "workspace change sync");
     drop_batch_graphs(ctx);
     ctx->bkey = 0;
     ctx->bcount = 0;
+    ctx->bauto_key = 0;
+    ctx->batch_err = nullptr;
     ctx->ws = bytes ? static_cast<char*>(d_ptr) : nullptr;
     ctx->ws_bytes = bytes;
     ctx->ws_owner = WS_NONE;
@@ -1182,6 +1279,85 @@ apsp_status_t apsp_validate(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const v
 
 namespace {
 
+// The cost model's four inputs for a batch: log2 of the largest n, log10 of
+// the batch's density (edges / sum of n (n - 1), clamped to 1e-9), log2 of
+// the graph count, and the share of the batch's work (sum of n^3) in graphs
+// with n > 256.
+void batch_features(int32_t count, const int32_t* h_sizes, double density, float* x)
+{
+    int32_t nmax = 1;
+    double all = 0.0, big = 0.0;
+    for (int32_t g = 0; g < count; ++g) {
+        nmax = std::max(nmax, h_sizes[g]);
+        const double w = (double)h_sizes[g] * h_sizes[g] * h_sizes[g];
+        all += w;
+        if (h_sizes[g] > 256) big += w;
+    }
+    x[0] = (float)std::log2((double)nmax);
+    x[1] = (float)std::log10(std::max(density, 1e-9));
+    x[2] = (float)std::log2((double)std::max(count, 1));
+    x[3] = (float)(all > 0.0 ? big / all : 0.0);
+}
+
+// First minimum of the batch candidates' predicted scores (outputs
+// kNumCandidates ..).
+int32_t pick_batch_candidate(const float* pred)
+{
+    int32_t choice = 0;
+    for (int32_t i = 1; i < kNumBatchCandidates; ++i)
+        if (pred[i] < pred[choice]) choice = i;
+    return choice;
+}
+
+// Scores the batch candidates for features x (device forward pass, one
+// read-back).
+apsp_status_t score_batch(apsp_ctx_t* ctx, const float* x, hipStream_t st, int32_t* choice)
+{
+    const int K = ctx->cm_K;
+    HIP_TRY(hipMemcpyAsync(ctx->cm_io, x, 4 * sizeof(float), hipMemcpyHostToDevice, st), "plan features upload");
+    HIP_TRY(apsp::launch_mlp_forward(ctx->cm_params, ctx->cm_norm, ctx->cm_io, 1, K, ctx->cm_ws, ctx->cm_io + 4, st),
+            "mlp forward");
+    std::vector<float> h(K);
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->cm_io + 4, K * sizeof(float), hipMemcpyDeviceToHost, st), "scores read-back");
+    HIP_TRY(hipStreamSynchronize(st), "plan sync");
+    *choice = pick_batch_candidate(h.data() + kNumCandidates);
+    return APSP_OK;
+}
+
+// Automatic plan of apsp_batched: the cost model's pick from the batch's
+// features (the density is counted on the device and read back), made once
+// per batch shape; the default candidate without a model with batch outputs.
+apsp_status_t batch_auto_plan(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, const void* data,
+                              const int64_t* d_offsets, const int32_t* d_sizes, const int32_t* h_sizes,
+                              hipStream_t st, apsp_opts_t* out)
+{
+    uint64_t key = 0xcbf29ce484222325ull ^ (uint64_t)dt;
+    for (int32_t g = 0; g < count; ++g) key = (key ^ (uint64_t)(uint32_t)h_sizes[g]) * 1099511628211ull;
+    key = (key ^ (uint64_t)count) * 1099511628211ull;
+    key ^= batch_model_ready(ctx) ? 0x9e3779b97f4a7c15ull : 0;
+    if (key != ctx->bauto_key || ctx->bauto_choice < 0) {
+        int32_t choice = kDefaultBatchCandidate;
+        if (batch_model_ready(ctx)) {
+            auto* tot = reinterpret_cast<unsigned long long*>(static_cast<char*>(ctx->d_scratch) + 224);
+            HIP_TRY(apsp::launch_batch_edges((apsp::DType)dt, data, d_offsets, d_sizes, count, tot, st),
+                    "batch edge count");
+            unsigned long long m = 0;
+            HIP_TRY(hipMemcpyAsync(&m, tot, sizeof m, hipMemcpyDeviceToHost, st), "edge count read-back");
+            HIP_TRY(hipStreamSynchronize(st), "edge count sync");
+            double pairs = 0.0;
+            for (int32_t g = 0; g < count; ++g) pairs += (double)h_sizes[g] * std::max(h_sizes[g] - 1, 0);
+            float x[4];
+            batch_features(count, h_sizes, pairs > 0.0 ? (double)m / pairs : 0.0, x);
+            apsp_status_t rc = score_batch(ctx, x, st, &choice);
+            if (rc) return rc;
+        }
+        ctx->bauto_key = key;
+        ctx->bauto_choice = choice;
+    }
+    batch_candidate_opts(ctx->bauto_choice, out);
+    return APSP_OK;
+}
+
 // Where a batched plan lives: the caller's workspace (apsp_batched) or the
 // library's fixed device scratch (apsp_batched_noalloc, no graph replay).
 struct PlanMem {
@@ -1210,14 +1386,27 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
 
+    // every option automatic: the cost model's batch plan (made once per
+    // batch shape), else the default candidate
+    apsp_opts_t auto_opts;
+    if (opts_all_auto(o)) {
+        if ((rc = batch_auto_plan(ctx, dt, count, data, d_offsets, d_sizes, h_sizes, st, &auto_opts))) return rc;
+        o = &auto_opts;
+    }
     // plan: largest graphs first (longest-processing-time order)
     uint64_t key = 1469598103934665603ull ^ (uint64_t)dt;
     for (int32_t g = 0; g < count; ++g) key = (key ^ (uint64_t)(uint32_t)h_sizes[g]) * 1099511628211ull;
     key ^= (uint64_t)count << 40;
+    key = (key ^ (uint64_t)(uint32_t)o->block) * 1099511628211ull;
+    key = (key ^ (uint64_t)(uint32_t)o->reserved[0]) * 1099511628211ull;
+    key = (key ^ (uint64_t)(uint32_t)o->tile) * 1099511628211ull;
     const bool rebuild = key != ctx->bkey || count != ctx->bcount || dt != ctx->bdtype;
     std::vector<int32_t> order;
     std::vector<int4> items;
     std::vector<apsp_ctx::Launch> launches;
+    std::vector<apsp::BatchTask> qtasks;
+    std::vector<int32_t> qoff;
+    int32_t qcounters = 0;
     if (rebuild) {
         order.resize(count);
         for (int32_t g = 0; g < count; ++g) order[g] = g;
@@ -1269,10 +1458,23 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
                     }
             });
         }
+        std::vector<int32_t> widths(count), subs(count);
+        for (int32_t g = 0; g < count; ++g) {
+            widths[g] = queue_width(o, h_sizes[g]);
+            subs[g] = queue_sub(o, h_sizes[g]);
+        }
+        const int nx = num_xcds(ctx);
+        apsp::build_xcd_queues(widths.data(), subs.data(), count, h_sizes, order, nx,
+                               (ctx->num_cus / nx) * apsp::batch_queue_resident_per_cu((apsp::DType)dt),
+                               kWsAlign / (int)sizeof(int32_t), apsp::TaskCost{}, qtasks, qoff, qcounters);
     }
-    // plan memory: [pointer record][order][items], in the caller's workspace
-    // or in the fixed scratch (after its counter word)
-    const size_t need = batched_ws_bytes(count, rebuild ? items.size() : ctx->litems.size());
+    // plan memory: [pointer record][ticket, error word][order][items][tasks]
+    // [counters], in the caller's workspace or in the fixed scratch (after
+    // its counter word)
+    const BatchLayout lay = batch_layout(count, rebuild ? items.size() : ctx->litems.size(),
+                                         rebuild ? qtasks.size() : ctx->qtasks.size(),
+                                         rebuild ? qcounters : ctx->qcounters);
+    const size_t need = lay.bytes;
     char* base;
     if (pm.fixed) {
         if (!ctx->fixed || need > kFixedScratchBytes - kWsAlign)
@@ -1287,21 +1489,30 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
         base = ctx->ws;
     }
     auto* d_bptrs = reinterpret_cast<apsp::BatchPtrs*>(base);
-    auto* d_order = reinterpret_cast<int32_t*>(base + kWsAlign);
-    auto* d_items = reinterpret_cast<int4*>(base + kWsAlign + align_up((size_t)count * sizeof(int32_t)));
+    auto* d_ticket = reinterpret_cast<uint32_t*>(base + lay.ticket);
+    auto* d_err = reinterpret_cast<uint32_t*>(base + lay.err);
+    auto* d_qoff = reinterpret_cast<int32_t*>(base + lay.qoff);
+    ctx->batch_err = d_err;
+    auto* d_order = reinterpret_cast<int32_t*>(base + lay.order);
+    auto* d_items = reinterpret_cast<int4*>(base + lay.items);
+    auto* d_tasks = reinterpret_cast<apsp::BatchTask*>(base + lay.tasks);
+    auto* d_counters = reinterpret_cast<int32_t*>(base + lay.counters);
     if (rebuild) {
         // the captured graphs (workspace path) belong to the previous plan;
         // they are dropped by the next call that would replay them
         ctx->border = std::move(order);
         ctx->litems = std::move(items);
         ctx->llaunches = std::move(launches);
+        ctx->qtasks = std::move(qtasks);
+        ctx->qoff = std::move(qoff);
+        ctx->qcounters = qcounters;
         ctx->bkey = key;
         ctx->bcount = count;
         ctx->bdtype = dt;
         ctx->ws_owner = WS_NONE;
         ctx->fixed_serial = 0;
     }
-    if (!pm.fixed && ctx->graph_key != ctx->bkey && (ctx->bexec || ctx->lexec)) {
+    if (!pm.fixed && ctx->graph_key != ctx->bkey && (ctx->bexec || ctx->lexec || ctx->qexec)) {
         // a replay of the previous plan may still be running
         HIP_TRY(hipStreamSynchronize(st), "plan change sync");
         drop_batch_graphs(ctx);
@@ -1319,6 +1530,15 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
             HIP_TRY(hipMemcpyAsync(d_items, ctx->litems.data(), ctx->litems.size() * sizeof(int4),
                                    hipMemcpyHostToDevice, st),
                     "plan upload");
+        if (!ctx->qtasks.empty())
+            HIP_TRY(hipMemcpyAsync(d_tasks, ctx->qtasks.data(), ctx->qtasks.size() * sizeof(apsp::BatchTask),
+                                   hipMemcpyHostToDevice, st),
+                    "plan upload");
+        if (!ctx->qoff.empty())
+            HIP_TRY(hipMemcpyAsync(d_qoff, ctx->qoff.data(), ctx->qoff.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st),
+                    "plan upload");
+        HIP_TRY(apsp::launch_fill_u32(d_err, 0u, 1, st), "error word reset");
         HIP_TRY(hipStreamSynchronize(st), "plan upload sync");
         if (pm.fixed)
             fixed_plan_claim(ctx);
@@ -1336,6 +1556,48 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
     const int grid = std::min<int>(count, ctx->num_cus * apsp::batched_resident_per_cu(kdt));
     const double terms = 0.0, bytes = 0.0;
 
+    if ((o->flags & APSP_FLAG_BATCH_QUEUE) &&
+        !(o->flags & (APSP_FLAG_BATCH_PERSISTENT | APSP_FLAG_BATCH_PER_GRAPH))) {
+        // dependency-driven schedule: one workgroup per task, tickets in
+        // topological order; zeroing the ticket and counters and the launch
+        // are replayed from one captured graph per batch shape
+        const int nx = (int)ctx->qoff.size() - 1;
+        int qmax = 0;
+        for (int x = 0; x < nx; ++x) qmax = std::max(qmax, ctx->qoff[x + 1] - ctx->qoff[x]);
+        const int ncnt = ctx->qcounters;
+        auto enqueue = [&](hipStream_t s2) -> hipError_t {
+            return apsp::launch_batch_queue(kdt, d_bptrs, d_tasks, d_qoff, nx, qmax, d_ticket, d_counters, ncnt, d_err,
+                                            s2);
+        };
+        return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
+            HIP_TRY(apsp::launch_batch_ptrs(d_bptrs, data, d_offsets, d_sizes, st), "batch pointer update");
+            if (pm.fixed || (o->flags & APSP_FLAG_BATCH_NO_GRAPH)) {
+                HIP_TRY(enqueue(st), "queue launch");
+                return APSP_OK;
+            }
+            if (!ctx->qexec) {
+                HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+                hipError_t le = enqueue(ctx->capture);
+                hipGraph_t g = nullptr;
+                hipError_t ce = hipStreamEndCapture(ctx->capture, &g);
+                if (le != hipSuccess) {
+                    if (g) hipGraphDestroy(g);
+                    return hip_fail(le, "queue capture launch");
+                }
+                HIP_TRY(ce, "end capture");
+                hipGraphExec_t ex = nullptr;
+                hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                if (ie != hipSuccess) {
+                    hipGraphDestroy(g);
+                    return hip_fail(ie, "graph instantiate");
+                }
+                ctx->qgraph = g;
+                ctx->qexec = ex;
+            }
+            HIP_TRY(hipGraphLaunch(ctx->qexec, st), "graph launch");
+            return APSP_OK;
+        });
+    }
     if (!(o->flags & (APSP_FLAG_BATCH_PERSISTENT | APSP_FLAG_BATCH_PER_GRAPH))) {
         // lock-step schedule: point the device record at this call's buffers,
         // then run the launch list (captured once per batch shape)
@@ -1494,6 +1756,20 @@ apsp_status_t apsp_batched_noalloc(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t cou
                           "apsp_batched_noalloc");
 }
 
+apsp_status_t apsp_batched_status(apsp_ctx_t* ctx, void* stream, uint32_t* h_flags)
+{
+    apsp_status_t rc;
+    if (!h_flags) return fail(APSP_E_ARG, "h_flags is NULL");
+    if ((rc = check_ctx(ctx))) return rc;
+    *h_flags = 0;
+    if (!ctx->batch_err) return APSP_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(h_flags, ctx->batch_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st), "status read");
+    HIP_TRY(apsp::launch_fill_u32(ctx->batch_err, 0u, 1, st), "status reset");
+    HIP_TRY(hipStreamSynchronize(st), "status sync");
+    return APSP_OK;
+}
+
 apsp_status_t apsp_profile_enable(apsp_ctx_t* ctx, int32_t on)
 {
     apsp_status_t rc;
@@ -1542,6 +1818,46 @@ apsp_status_t apsp_candidate(int32_t index, apsp_opts_t* out)
     out->closure = c.closure;
     out->cutover = c.cutover;
     out->flags = c.flags;
+    return APSP_OK;
+}
+
+int32_t apsp_batch_candidate_count(void) { return kNumBatchCandidates; }
+
+apsp_status_t apsp_batch_candidate(int32_t index, apsp_opts_t* out)
+{
+    if (!out) return fail(APSP_E_ARG, "output is NULL");
+    if (index < 0 || index >= kNumBatchCandidates)
+        return fail(APSP_E_ARG, "batch candidate %d of %d", index, kNumBatchCandidates);
+    batch_candidate_opts(index, out);
+    return APSP_OK;
+}
+
+apsp_status_t apsp_plan_batch(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, const int32_t* h_sizes,
+                              double density, apsp_opts_t* out, int32_t* h_choice)
+{
+    apsp_status_t rc;
+    if ((rc = check_dtype(dt))) return rc;
+    if (!out) return fail(APSP_E_ARG, "output is NULL");
+    if (count < 1 || !h_sizes || density < 0.0) return fail(APSP_E_ARG, "bad batch plan features");
+    if ((rc = check_ctx(ctx))) return rc;
+    int32_t choice = kDefaultBatchCandidate;
+    if (h_choice) *h_choice = -1;
+    if (batch_model_ready(ctx)) {
+        float x[4];
+        batch_features(count, h_sizes, density, x);
+        if ((rc = score_batch(ctx, x, nullptr, &choice))) return rc;
+        if (h_choice) *h_choice = choice;
+    }
+    batch_candidate_opts(choice, out);
+    return APSP_OK;
+}
+
+apsp_status_t apsp_batched_choice(apsp_ctx_t* ctx, int32_t* h_choice)
+{
+    apsp_status_t rc;
+    if (!h_choice) return fail(APSP_E_ARG, "h_choice is NULL");
+    if ((rc = check_ctx(ctx))) return rc;
+    *h_choice = ctx->bauto_choice;
     return APSP_OK;
 }
 
@@ -1810,9 +2126,10 @@ apsp_status_t apsp_plan(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, double dens
     if ((rc = check_dtype(dt))) return rc;
     if (!out) return fail(APSP_E_ARG, "output is NULL");
     if (n < 0 || batch < 1 || density < 0.0) return fail(APSP_E_ARG, "bad plan features");
+    if (batch != 1) return fail(APSP_E_ARG, "apsp_plan plans one graph (batch = 1); use apsp_plan_batch");
     if ((rc = check_ctx(ctx))) return rc;
     if (h_choice) *h_choice = -1;
-    if (!ctx->cm_params || ctx->cm_K != kNumCandidates) {
+    if (!model_ready(ctx)) {
         *out = apsp_opts_t{};
         out->algo = n <= 4096 ? APSP_ALGO_FW : APSP_ALGO_RKLEENE;
         out->cutover = n <= 4096 ? 0 : 4096;
@@ -1823,10 +2140,11 @@ apsp_status_t apsp_plan(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, double dens
                   connected ? 1.f : 0.f};
     HIP_TRY(hipMemcpy(ctx->cm_io, x, sizeof x, hipMemcpyHostToDevice), "plan features upload");
     if ((rc = apsp_costmodel_forward(ctx, ctx->cm_io, 1, ctx->cm_io + 4, nullptr))) return rc;
-    float pred[kNumCandidates];
-    HIP_TRY(hipMemcpy(pred, ctx->cm_io + 4, sizeof pred, hipMemcpyDeviceToHost), "plan scores download");
+    std::vector<float> pred(ctx->cm_K);
+    HIP_TRY(hipMemcpy(pred.data(), ctx->cm_io + 4, pred.size() * sizeof(float), hipMemcpyDeviceToHost),
+            "plan scores download");
     // first minimum among the candidates this dtype can run
-    const int32_t choice = pick_candidate(dt, pred);
+    const int32_t choice = pick_candidate(dt, pred.data());
     if (h_choice) *h_choice = choice;
     return apsp_candidate(choice, out);
 }

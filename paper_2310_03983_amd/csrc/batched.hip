@@ -234,6 +234,169 @@ __global__ __launch_bounds__(dev::kCloseWideThreads) void k_bpivot(const BatchPt
     dev::close_block_wide<S>(X, ld, w, reinterpret_cast<T*>(smem));
 }
 
+// ---------------------------------------------------------------------------
+// Dependency-driven schedule: one launch runs every task of every graph --
+// first pivot closures, panel tiles, remainder tiles, fused next pivots of
+// its Floyd-Warshall rounds -- from ticket queues, one queue per XCD.  A
+// workgroup reads which XCD it runs on, takes the next ticket of that XCD's
+// queue, waits until the counters its task depends on reach their targets,
+// runs the task and increments its own counter.  All tasks of a graph are
+// in one queue, so a tile is written and read through one L2: a producer
+// only waits for its stores to complete before it signals (no write-back of
+// the L2), and a consumer invalidates its CU's L1 before it reads.  Each queue lists its tasks in a
+// topological order (every task a task waits for has a smaller ticket in
+// the same queue) and a workgroup that holds a ticket is running, so every
+// queue drains.  Waits are bounded: past kSpinLimit polls the workgroup
+// records the overrun in the error word and runs the task anyway, so every
+// launch ends.  The grid holds qlen_max workgroups per XCD (workgroups are
+// dispatched to the XCDs in turn); a workgroup whose queue is empty returns.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSpinLimit = 1u << 20;
+constexpr int kTicketStride = 64;   // one 256-byte slot per XCD queue
+
+// Polls with an atomic read-modify-write (adding 0), which is performed
+// where the producers' increments are: in this XCD's L2.
+__device__ __forceinline__ void wait_counter(int32_t* c, int32_t need, uint32_t* err)
+{
+    uint32_t polls = 0;
+    while (__hip_atomic_fetch_add(c, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (++polls > kSpinLimit) {
+            atomicOr(err, 1u);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// One workgroup per task: each workgroup takes a ticket when it starts.
+template <class S>
+__global__ __launch_bounds__(dev::kCloseWideThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_bqueue(const BatchPtrs* __restrict__ bp, const BatchTask* __restrict__ tasks, const int32_t* __restrict__ qoff,
+              int nxcd, uint32_t* tickets, int32_t* counters, uint32_t* err)
+{
+    using T = typename S::T;
+    using P = typename S::P;
+    constexpr int KT = 16;
+    constexpr int kTileBytes = 2 * 2 * (KT / 2) * (kB + 2) * (int)sizeof(P);
+    constexpr int kBytes = kTileBytes > dev::kCloseLdsWords * 4 ? kTileBytes : dev::kCloseLdsWords * 4;
+    __shared__ __attribute__((aligned(16))) char smem[kBytes];
+    __shared__ int slot;
+    auto As = reinterpret_cast<P (*)[KT / 2][kB + 2]>(smem);
+    auto Bs = reinterpret_cast<P (*)[KT / 2][kB + 2]>(smem + kTileBytes / 2);
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        // XCC_ID (bits 3:0 of hardware register 20): the XCD this workgroup runs on
+        const int x = (int)((unsigned)__builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) % (unsigned)nxcd);
+        const int q0 = qoff[x], len = qoff[x + 1] - q0;
+        const int tk = len > 0 ? (int)atomicAdd(tickets + x * kTicketStride, 1u) : 0;
+        slot = tk < len ? q0 + tk : -1;
+    }
+    __syncthreads();
+    const int q = slot;
+    if (q < 0) return;
+    const BatchTask t = tasks[q];
+    if (tid == 0) {
+        if (t.wait0 >= 0) wait_counter(counters + t.wait0, t.need0, err);
+        if (t.wait1 >= 0) wait_counter(counters + t.wait1, t.need1, err);
+        // the inputs were written on this XCD and sit in its L2; an
+        // agent-scope acquire drops the older copies this CU's L1 may hold
+        // (an invalidation at workgroup scope would leave the L1 alone)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();   // every lane reads the task's inputs after the invalidation
+    const int n = bp->sizes[t.graph];
+    T* D = static_cast<T*>(bp->data) + bp->offsets[t.graph];
+    const int64_t ld = n;
+    const int W = t.width;              // the graph's round width: 64 or 128
+    const int k0 = t.round * W, bk = min(W, n - k0);
+    T* piv = D + (int64_t)k0 * ld + k0;
+    // one product call site per width and one closure call site
+    T* X = piv;   // block closed at the end (close and fused tasks)
+    int w = bk;
+    if (t.kind != kTaskClose) {
+        const T* A;
+        const T* B;
+        T* C;
+        int M, N;
+        if (t.kind == kTaskRow) {            // R_KJ <- X* (min,+) R_KJ
+            const int o0 = t.a * W;
+            C = D + (int64_t)k0 * ld + o0;
+            A = piv;
+            B = C;
+            M = bk;
+            N = min(W, n - o0);
+        } else if (t.kind == kTaskCol) {     // C_IK <- C_IK (min,+) X*
+            const int o0 = t.a * W;
+            C = D + (int64_t)o0 * ld + k0;
+            A = C;
+            B = piv;
+            M = min(W, n - o0);
+            N = bk;
+        } else {                             // D_IJ <- min(D_IJ, C_IK (min,+) R_KJ); fused: (a, a)
+            const int r0 = t.a * W, c0 = t.b * W;
+            C = D + (int64_t)r0 * ld + c0;
+            A = D + (int64_t)r0 * ld + k0;
+            B = D + (int64_t)k0 * ld + c0;
+            M = min(W, n - r0);
+            N = min(W, n - c0);
+            X = C;
+            w = M;
+        }
+        if (t.sub >= 0) {
+            // one 64 x 64 sub-tile (si, sj) of the tile: rows of C and A, columns of C and B
+            const int si = (t.sub & 0xff) * 64, sj = (t.sub >> 8) * 64;
+            C += (int64_t)si * ld + sj;
+            A += (int64_t)si * ld;
+            B += sj;
+            M = min(64, M - si);
+            N = min(64, N - sj);
+        }
+        if (W == kB && t.sub < 0)
+            dev::mp_tile<S, kB, kB, KT, 8, 4, true>(A, ld, B, ld, C, ld, M, N, 0, 0, 0, bk, false, nullptr, As, Bs);
+        else
+            dev::mp_tile<S, 64, 64, 32, 4, 2, true>(A, ld, B, ld, C, ld, M, N, 0, 0, 0, bk, false, nullptr,
+                                                   reinterpret_cast<P (*)[16][66]>(smem),
+                                                   reinterpret_cast<P (*)[16][66]>(smem + 2 * 16 * 66 * sizeof(P)));
+    }
+    if (t.kind == kTaskClose || t.kind == kTaskFused) {
+        // the fused task: round t.round's update of the next pivot block,
+        // then the closure that starts round a
+        __syncthreads();   // the block's stores are visible to the whole workgroup
+        dev::close_block_wide<S>(X, ld, w, reinterpret_cast<T*>(smem));
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // this lane's stores have reached the L2
+    __syncthreads();                   // ... and every lane's
+    if (tid == 0 && t.signal >= 0)
+        __hip_atomic_fetch_add(counters + t.signal, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Edges of every graph of a batch (finite off-diagonal entries), summed into
+// *total: one workgroup per graph (the batch planner's density input).
+template <class T>
+__device__ __forceinline__ bool finite_entry(T v);
+template <>
+__device__ __forceinline__ bool finite_entry<uint32_t>(uint32_t v) { return v < kInfI32; }
+template <>
+__device__ __forceinline__ bool finite_entry<float>(float v) { return v < __builtin_inff(); }
+
+template <class T>
+__global__ __launch_bounds__(256) void k_batch_edges(const T* __restrict__ data, const int64_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ sizes,
+                                                     unsigned long long* __restrict__ total)
+{
+    const int g = blockIdx.x;
+    const int n = sizes[g];
+    const T* D = data + offsets[g];
+    const int nn = n * n;   // n <= 1024 in a batch
+    uint32_t cnt = 0;
+    for (int e = threadIdx.x; e < nn; e += 256) {
+        const int r = e / n, c = e - r * n;
+        cnt += (r != c) && finite_entry<T>(D[e]);
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(total, (unsigned long long)cnt);
+}
+
 __global__ void k_set_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, const int32_t* sizes)
 {
     if (threadIdx.x == 0) {
@@ -302,6 +465,52 @@ hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const in
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_queue(DType dt, const BatchPtrs* bp, const BatchTask* tasks, const int32_t* qoff, int nxcd,
+                              int qlen_max, uint32_t* tickets, int32_t* counters, int ncounters, uint32_t* err,
+                              hipStream_t st)
+{
+    if (qlen_max <= 0) return hipSuccess;
+    // tickets and counters start at zero on every launch (fill kernels, so
+    // the sequence can be captured in a graph)
+    hipError_t e = launch_fill_u32(tickets, 0u, (int64_t)nxcd * kTicketStride, st);
+    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, ncounters, st);
+    if (e != hipSuccess) return e;
+    const unsigned grid = (unsigned)nxcd * (unsigned)qlen_max;
+    if (dt == I32)
+        hipLaunchKernelGGL(k_bqueue<dev::SemI32>, dim3(grid), dim3(dev::kCloseWideThreads), 0, st, bp, tasks, qoff,
+                           nxcd, tickets, counters, err);
+    else
+        hipLaunchKernelGGL(k_bqueue<dev::SemF32>, dim3(grid), dim3(dev::kCloseWideThreads), 0, st, bp, tasks, qoff,
+                           nxcd, tickets, counters, err);
+    return hipGetLastError();
+}
+
+int batch_queue_ticket_words(int nxcd) { return nxcd * kTicketStride; }
+
+int batch_queue_resident_per_cu(DType dt)
+{
+    int blocks = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, dt == I32 ? reinterpret_cast<const void*>(&k_bqueue<dev::SemI32>)
+                           : reinterpret_cast<const void*>(&k_bqueue<dev::SemF32>),
+        dev::kCloseWideThreads, 0);
+    return (e == hipSuccess && blocks > 0) ? blocks : 1;
+}
+
+hipError_t launch_batch_edges(DType dt, const void* data, const int64_t* offsets, const int32_t* sizes, int count,
+                              unsigned long long* total, hipStream_t st)
+{
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(total), 0u, 2, st);
+    if (e != hipSuccess || count <= 0) return e;
+    if (dt == F32)
+        hipLaunchKernelGGL(k_batch_edges<float>, dim3(count), dim3(256), 0, st, (const float*)data, offsets, sizes,
+                           total);
+    else
+        hipLaunchKernelGGL(k_batch_edges<uint32_t>, dim3(count), dim3(256), 0, st, (const uint32_t*)data, offsets,
+                           sizes, total);
     return hipGetLastError();
 }
 

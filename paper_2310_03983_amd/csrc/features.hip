@@ -22,9 +22,13 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Parent reads go through the caches and may return an older parent: every
+// value a vertex ever had is an ancestor of it (parents only move up), so a
+// walk still ends at a vertex of the same tree, and any link is changed only
+// by a compare-and-swap, which sees the current value.
 __device__ __forceinline__ int32_t load_parent(int32_t* parent, int32_t x)
 {
-    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x)
@@ -68,8 +72,9 @@ __global__ __launch_bounds__(kThreads) void k_parent_init(int32_t* parent, int32
     for (int32_t v = blockIdx.x * kThreads + threadIdx.x; v < n; v += gridDim.x * kThreads) parent[v] = v;
 }
 
-// Rows are taken by workgroups; the row's own root is found once and edges
-// whose other end already has that root as its parent skip the union.
+// Rows are taken by workgroups; the row's root is found once, and an edge
+// whose other end already has that vertex as its parent is in the same tree
+// (both ends hang below it) and skips the union.
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ D, int32_t n, int64_t ld,
                                                           int32_t* parent, unsigned long long* edges)
@@ -77,12 +82,12 @@ __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ 
     uint32_t cnt = 0;
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const T* row = D + (int64_t)i * ld;
-        int32_t ri = find_root(parent, i);
+        const int32_t ri = find_root(parent, i);
         for (int32_t j = threadIdx.x; j < n; j += kThreads) {
             if (j == i || !edge<T>(row[j])) continue;
             ++cnt;
-            if (load_parent(parent, j) == ri && load_parent(parent, ri) == ri) continue;
-            unite(parent, i, j);
+            if (load_parent(parent, j) == ri) continue;
+            unite(parent, ri, j);
         }
     }
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);

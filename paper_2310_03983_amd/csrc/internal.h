@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "batch_plan.h"
+
 namespace apsp {
 
 // I32P16: int32 data whose min-plus products run in capped 16-bit arithmetic
@@ -119,6 +121,20 @@ hipError_t launch_batch_ptrs(BatchPtrs* bp, void* data, const int64_t* offsets, 
 hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const int4* items, int count,
                               hipStream_t st);
 int batched_round_width();
+
+// Zeroes the per-XCD tickets and counters[0..ncounters), then launches
+// nxcd * qlen_max workgroups; queue x holds tasks[qoff[x] .. qoff[x+1]);
+// *err gets bit 0 if a wait overran.
+hipError_t launch_batch_queue(DType dt, const BatchPtrs* bp, const BatchTask* tasks, const int32_t* qoff, int nxcd,
+                              int qlen_max, uint32_t* tickets, int32_t* counters, int ncounters, uint32_t* err,
+                              hipStream_t st);
+// Finite off-diagonal entries of every graph of a batch, summed into *total
+// (uint64, zeroed first).
+hipError_t launch_batch_edges(DType dt, const void* data, const int64_t* offsets, const int32_t* sizes, int count,
+                              unsigned long long* total, hipStream_t st);
+// 32-bit words of ticket space for nxcd queues (one 256-byte slot each).
+int batch_queue_ticket_words(int nxcd);
+int batch_queue_resident_per_cu(DType dt);
 
 // Enqueues the counter reset and the persistent batched kernel.
 hipError_t launch_batched(DType dt, const BatchArgs& a, int grid, hipStream_t st);

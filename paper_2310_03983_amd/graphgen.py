@@ -30,6 +30,7 @@ GOLDEN = 0x9E3779B97F4A7C15
 M64 = (1 << 64) - 1
 
 EDGE, WEIGHT, NSTREAM, PSTREAM, PERM, SRC, CHAIN = 1, 2, 3, 4, 5, 6, 7
+COUNTSTREAM, HISTREAM, LOSTREAM = 8, 9, 10   # batch sweep: graph count, largest n, smallest n
 
 
 # --------------------------------------------------------------------------
@@ -295,6 +296,48 @@ def sweep_graph_i32(sg: SweepGraph, lo: int = 1, hi: int = 1000) -> np.ndarray:
     if sg.chain:
         add_chain_i32(W, sg.seed, lo, hi)
     return W
+
+
+@dataclass(frozen=True)
+class BatchSpec:
+    """One batch of the batch sweep: `count` graphs with n log-uniform in
+    [n_lo, n_hi] and p uniform in [p_lo, p_hi], drawn like the 512-graph
+    workload with its own base seed."""
+    b: int
+    count: int
+    n_lo: int
+    n_hi: int
+    p_lo: float
+    p_hi: float
+    base_seed: int
+
+    def graphs(self):
+        return batch_ragged(self.count, self.n_lo, self.n_hi, self.p_lo, self.p_hi, self.base_seed)
+
+
+def batch_sweep(count: int = 200, base_seed: int = 6):
+    """Batches for timing the batched schedules (the batch cost model's
+    data).  Batches 0..159: graph count log-uniform in [16, 768], largest n
+    log-uniform in [96, 1024], smallest n 32 or 64, p uniform in
+    [0.02, p_hi] with p_hi uniform in [0.05, 0.3].  Batches 160..199 cover
+    large dense batches more closely: count log-uniform in [256, 768],
+    smallest n 32, largest n log-uniform in [384, 640], p_hi uniform in
+    [0.2, 0.3].  Costs 1..100 as in the 512-graph workload."""
+    out = []
+    for b in range(count):
+        s = graph_seed(base_seed, b)
+        if b < 160:
+            cnt = log_uniform_int(s, COUNTSTREAM, 16, 768)
+            n_hi = log_uniform_int(s, HISTREAM, 96, 1024)
+            n_lo = 32 if u01(h(s, LOSTREAM, 0)) < 0.5 else 64
+            p_hi = uniform(s, PSTREAM, 0.05, 0.3)
+        else:
+            cnt = log_uniform_int(s, COUNTSTREAM, 256, 768)
+            n_hi = log_uniform_int(s, HISTREAM, 384, 640)
+            n_lo = 32
+            p_hi = uniform(s, PSTREAM, 0.2, 0.3)
+        out.append(BatchSpec(b, cnt, n_lo, n_hi, 0.02, p_hi, 1000 + b))
+    return out
 
 
 def pack_batch(mats):

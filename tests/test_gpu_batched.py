@@ -39,21 +39,30 @@ def test_batched_edge_sizes(native, dev):
     rng = np.random.default_rng(900)
     sizes = [0, 1, 2, 3, 31, 127, 128, 129, 200, 255, 256, 257, 511, 512, 513, 1000, 1024, 5]
     mats = [rand_graph(rng, n, min(0.5, 3.0 / max(n, 1))) for n in sizes]
-    for kw in ({}, {"batch_graph": False}, {"batch_persistent": True},
-               {"batch_persistent": True, "batch_graph": False}, {"batch_per_graph": True}):
+    sub = native.make_opts(batch_queue=True, tile=64)
+    sub.reserved[0] = 128
+    for kw in ({}, {"batch_lockstep": True}, {"batch_lockstep": True, "batch_graph": False}, {"batch_persistent": True},
+               {"batch_persistent": True, "batch_graph": False}, {"batch_per_graph": True},
+               {"batch_queue": True}, {"batch_queue": True, "batch_graph": False}, {"batch_queue": True, "block": 64},
+               {"opts": sub}):
         flat, off_d, sz_d, hs, off = pack(mats, dev)
         flags = kw
         native.apsp_batched(flat, off_d, sz_d, hs, **kw)
         for W, got in zip(mats, unpack(flat, off, hs)):
             np.testing.assert_array_equal(got, oracle.fw_i32(W), err_msg=f"n={W.shape[0]} {flags}")
+        assert native.apsp_batched_status() == 0, flags
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batched_f32(native, dev, persistent):
+SCHEDS = {"auto": {}, "lockstep": {"batch_lockstep": True}, "persistent": {"batch_persistent": True},
+          "queue": {"batch_queue": True}, "queue_sub": {"batch_queue": True, "tile": 64}}
+
+
+@pytest.mark.parametrize("sched", list(SCHEDS))
+def test_batched_f32(native, dev, sched):
     rng = np.random.default_rng(901)
     mats = [rand_graph(rng, n, 4.0 / n, dtype="f32") for n in (40, 130, 300, 77)]
     flat, off_d, sz_d, hs, off = pack(mats, dev)
-    native.apsp_batched(flat, off_d, sz_d, hs, batch_persistent=persistent)
+    native.apsp_batched(flat, off_d, sz_d, hs, **SCHEDS[sched])
     for W, got in zip(mats, unpack(flat, off, hs)):
         ref = oracle.fw_f64(W.astype(np.float64))
         assert np.array_equal(np.isinf(got), np.isinf(ref))
@@ -61,8 +70,8 @@ def test_batched_f32(native, dev, persistent):
         assert (np.abs(got[fin] - ref[fin]) <= 1e-5 * ref[fin]).all()
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batched_graph_replays_and_buffer_swaps(native, dev, persistent):
+@pytest.mark.parametrize("sched", list(SCHEDS))
+def test_batched_graph_replays_and_buffer_swaps(native, dev, sched):
     # the captured launch is replayed several times, on two different buffers,
     # with unrelated eager work and synchronisations in between
     rng = np.random.default_rng(902)
@@ -72,7 +81,7 @@ def test_batched_graph_replays_and_buffer_swaps(native, dev, persistent):
     for rep in range(4):
         flat, off_d, sz_d, hs, off = bufs[rep % 2]
         flat.copy_(torch.from_numpy(gg.pack_batch(mats)[0]).to(dev))
-        native.apsp_batched(flat, off_d, sz_d, hs, batch_persistent=persistent)
+        native.apsp_batched(flat, off_d, sz_d, hs, **SCHEDS[sched])
         junk = torch.arange(1000, device=dev).sum()   # eager work between replays
         torch.cuda.synchronize()
         assert int(junk) == 499500
@@ -93,17 +102,18 @@ def test_batched_one_launch_plans_and_plan_switches(native, dev):
         mats, refs = cases[rep % 2]
         flat, off_d, sz_d, hs, off = bufs[id(mats)][(rep // 2) % 2]
         flat.copy_(torch.from_numpy(gg.pack_batch(mats)[0]).to(dev))
-        native.apsp_batched(flat, off_d, sz_d, hs)
+        native.apsp_batched(flat, off_d, sz_d, hs, batch_lockstep=True)
         for ref, got in zip(refs, unpack(flat, off, hs)):
             np.testing.assert_array_equal(got, ref, err_msg=f"call {rep}")
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batched_workload_512(native, dev, persistent):
+@pytest.mark.parametrize("sched", list(SCHEDS))
+def test_batched_workload_512(native, dev, sched):
     batch = gg.batch_ragged()
     mats = [gg.batch_graph_i32(b) for b in batch]
     flat, off_d, sz_d, hs, off = pack(mats, dev)
-    native.apsp_batched(flat, off_d, sz_d, hs, batch_persistent=persistent)
+    native.apsp_batched(flat, off_d, sz_d, hs, **SCHEDS[sched])
+    assert native.apsp_batched_status() == 0
     got = unpack(flat, off, hs)
     for b, W, g in zip(batch, mats, got):
         np.testing.assert_array_equal(g, oracle.fw_i32(W, threads=8), err_msg=f"graph {b.g} n={b.n}")

@@ -156,10 +156,10 @@ def test_plan_for_fp32_skips_packed_candidates(native, dev):
     assert ch in packed
     for n, dens in ((16384, 0.01), (2048, 0.3), (300, 0.01), (8192, 0.001)):
         X = torch.tensor([[np.log2(n), np.log10(dens), 0.0, 1.0]], dtype=torch.float32, device=dev)
-        out = torch.empty((1, Kc), dtype=torch.float32, device=dev)
+        out = torch.empty((1, model["K"]), dtype=torch.float32, device=dev)
         native.apsp_costmodel_forward(X, out)
         torch.cuda.synchronize()
-        scores = out.cpu().numpy()[0]
+        scores = out.cpu().numpy()[0][:Kc]          # the single-graph outputs come first
         allowed = [i for i in range(Kc) if i not in packed]
         o, ch = native.apsp_plan(n, dens, dtype="float32")
         assert ch == allowed[int(np.argmin(scores[allowed]))]
@@ -256,3 +256,59 @@ def test_choose_model_pick_and_exhaustive_fallback(native, dev):
     # fp32 graphs never get a capped 16-bit candidate
     _, _, _, tf = autotune.choose(Wd.float(), exhaustive=True, budget_s=0.05)
     assert all(not (native.apsp_candidate(i).flags & native.FLAG_PACKED16) for i in tf)
+
+
+def test_joint_model_gain_on_held_out_batches(native, dev):
+    """Retrains the joint model (single-graph and batch outputs) from the
+    committed timings (`autotune sweep` and `autotune batch` on this GPU) and
+    checks the gain on held-out data: on the 40 held-out batches (120..159) the
+    network's batch picks lose less time against exhaustive tuning than the
+    best static batch plan and than the former fixed lock-step plan; on the
+    50 held-out graphs the single-graph picks beat the best static plan and
+    the size rule.  The regret values are parity-unpinned (data)."""
+    import json
+    import os
+    from paper_2310_03983_amd import autotune
+    data = os.path.join(os.path.dirname(autotune.__file__), "data")
+    db = json.load(open(os.path.join(data, "sweep200_timings.json")))
+    bdb = json.load(open(os.path.join(data, "batch_sweep_timings.json")))
+    assert all(r["agree"] for r in bdb["records"].values())
+    model = autotune.train_joint(db, list(range(150)), bdb, autotune.BATCH_TRAIN, steps=4000)
+    assert model["K"] == native.apsp_candidate_count() + native.apsp_batch_candidate_count()
+    assert model["loss_last"] < 0.05 * model["loss_first"]
+    eb = autotune.evaluate_batches(bdb, model, autotune.BATCH_TEST, autotune.BATCH_TRAIN)
+    es = autotune.evaluate(db, model, list(range(150, 200)), list(range(150)))
+    print(json.dumps({"batch": eb, "single": es}))
+    assert eb["batches"] == 40
+    assert eb["mlp"]["mean_regret"] < eb["static_best"]["mean_regret"]
+    assert eb["mlp"]["mean_regret"] < eb["lockstep"]["mean_regret"]
+    assert es["mlp"]["mean_regret"] < es["static_best"]["mean_regret"]
+    assert es["mlp"]["mean_regret"] < es["size_rule"]["mean_regret"]
+    # the shipped model is this joint model and shows the same gain
+    shipped = json.load(open(os.path.join(data, "costmodel_mlp.json")))
+    assert shipped["K"] == model["K"]
+    eb2 = autotune.evaluate_batches(bdb, shipped, autotune.BATCH_TEST, autotune.BATCH_TRAIN)
+    assert eb2["mlp"]["mean_regret"] < eb2["static_best"]["mean_regret"]
+
+
+def test_batched_auto_plan_is_the_model_pick(native, dev):
+    """apsp_batched with no options plans from the batch's features (density
+    counted on the device) with the shipped joint model: the choice equals
+    apsp_plan_batch's for the host-computed features, and every graph's
+    distances equal the oracle's."""
+    from paper_2310_03983_amd import autotune, graphgen as gg
+    native.apsp_costmodel_load(native.MODEL_PATH)
+    for spec in gg.batch_sweep()[120:124]:
+        mats = [gg.batch_graph_i32(g) for g in spec.graphs()]
+        f = autotune.batch_features(mats)
+        flat, off, sz = gg.pack_batch(mats)
+        flat_d = torch.from_numpy(flat).to(dev)
+        native.apsp_batched(flat_d, torch.from_numpy(off).to(dev), torch.from_numpy(sz).to(dev), sz.tolist())
+        got = native.apsp_batched_choice()
+        _, want = native.apsp_plan_batch(sz.tolist(), 10.0 ** f[1])
+        assert got == want and 0 <= got < native.apsp_batch_candidate_count(), spec.b
+        h = flat_d.cpu().numpy()
+        for o, n, W in zip(off, sz, mats):
+            np.testing.assert_array_equal(h[o:o + n * n].reshape(n, n), oracle.fw_i32(W, threads=8),
+                                          err_msg=f"batch {spec.b} n={n}")
+        assert native.apsp_batched_status() == 0
