@@ -10,8 +10,12 @@
 // so parent[x] <= x always holds, every chain strictly decreases and every
 // walk ends; a failed swap returns the root's new parent, from which the
 // walk resumes.  Finds halve the path by swapping a vertex's parent for its
-// grandparent (again only by compare-and-swap).  A second pass counts the
+// grandparent (again only by compare-and-swap), and the far end of a joined
+// edge is pointed straight at the root the join ended with, so that the
+// common case -- an edge inside the tree, whose far end hangs right below the
+// root -- costs one cached read.  A second pass (one workgroup) counts the
 // roots: the graph is weakly connected iff there is exactly one.
+#include "device.h"
 #include "internal.h"
 
 #include <algorithm>
@@ -43,21 +47,29 @@ __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x)
     return x;
 }
 
-__device__ __forceinline__ void unite(int32_t* parent, int32_t a, int32_t b)
+// Joins the tree of j (a neighbour of the row's vertex) with the row's tree,
+// whose root was ri, and leaves in ri a root the two trees then had; j is
+// then pointed straight at that root, so later edges to j take the fast test.
+__device__ __forceinline__ void join(int32_t* parent, int32_t& ri, int32_t j)
 {
-    int32_t ra = find_root(parent, a), rb = find_root(parent, b);
-    while (ra != rb) {
-        if (ra > rb) {
-            const int32_t t = ra;
-            ra = rb;
-            rb = t;
+    int32_t a = find_root(parent, ri), b = find_root(parent, j);
+    while (a != b) {
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
         }
-        // hook the larger root rb under ra, if rb is still a root
-        const int32_t old = atomicCAS(parent + rb, rb, ra);
-        if (old == rb) return;
-        rb = find_root(parent, old);   // rb was hooked meanwhile: continue from its new root
-        ra = find_root(parent, ra);
+        // hook the larger root b under a, if b is still a root
+        const int32_t old = atomicCAS(parent + b, b, a);
+        if (old == b) break;
+        b = find_root(parent, old);   // b was hooked meanwhile: continue from its new root
+        a = find_root(parent, a);
     }
+    ri = a;
+    // a is an ancestor of j and not above j's current parent only if the
+    // parent is already a or higher; otherwise move j up to a
+    const int32_t pj = load_parent(parent, j);
+    if (pj > a) atomicCAS(parent + j, pj, a);
 }
 
 template <class T>
@@ -67,28 +79,61 @@ __device__ __forceinline__ bool edge<uint32_t>(uint32_t w) { return w < kInfI32;
 template <>
 __device__ __forceinline__ bool edge<float>(float w) { return w < __builtin_inff(); }
 
-__global__ __launch_bounds__(kThreads) void k_parent_init(int32_t* parent, int32_t n)
+// Zeroes the two counters and makes every vertex its own root.
+__global__ __launch_bounds__(kThreads) void k_features_init(int32_t* parent, int32_t n, unsigned long long* edges,
+                                                            uint32_t* roots)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *edges = 0ull;
+        *roots = 0u;
+    }
     for (int32_t v = blockIdx.x * kThreads + threadIdx.x; v < n; v += gridDim.x * kThreads) parent[v] = v;
 }
 
-// Rows are taken by workgroups; the row's root is found once, and an edge
-// whose other end already has that vertex as its parent is in the same tree
-// (both ends hang below it) and skips the union.
+// Rows are taken by workgroups and read four elements per access, four
+// accesses in flight per lane.  Each lane keeps a root of the row's tree; an
+// edge whose other end has that vertex as its parent is already inside the
+// tree and skips the join.
+template <class T>
+__device__ __forceinline__ void visit(int32_t* parent, int32_t& ri, int32_t r, int32_t c, T w, uint32_t& cnt)
+{
+    if (c == r || !edge<T>(w)) return;
+    ++cnt;
+    if (load_parent(parent, c) != ri) join(parent, ri, c);
+}
+
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ D, int32_t n, int64_t ld,
                                                           int32_t* parent, unsigned long long* edges)
 {
+    using V = dev::Pair2<dev::Pair2<T>>;   // four elements, one dwordx4 access
+    constexpr int kStep = 4 * kThreads;
     uint32_t cnt = 0;
-    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const T* row = D + (int64_t)i * ld;
-        const int32_t ri = find_root(parent, i);
-        for (int32_t j = threadIdx.x; j < n; j += kThreads) {
-            if (j == i || !edge<T>(row[j])) continue;
-            ++cnt;
-            if (load_parent(parent, j) == ri) continue;
-            unite(parent, ri, j);
+    for (int32_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const T* row = D + (int64_t)r * ld;
+        int32_t ri = find_root(parent, r);
+        int32_t c = threadIdx.x * 4;
+        for (; c + 3 * kStep + 3 < n; c += 4 * kStep) {
+            V v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = dev::ld_vec<V>(row + c + q * kStep);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t c0 = c + q * kStep;
+                visit<T>(parent, ri, r, c0, v[q].x.x, cnt);
+                visit<T>(parent, ri, r, c0 + 1, v[q].x.y, cnt);
+                visit<T>(parent, ri, r, c0 + 2, v[q].y.x, cnt);
+                visit<T>(parent, ri, r, c0 + 3, v[q].y.y, cnt);
+            }
         }
+        for (; c + 3 < n; c += kStep) {
+            const V v = dev::ld_vec<V>(row + c);
+            visit<T>(parent, ri, r, c, v.x.x, cnt);
+            visit<T>(parent, ri, r, c + 1, v.x.y, cnt);
+            visit<T>(parent, ri, r, c + 2, v.y.x, cnt);
+            visit<T>(parent, ri, r, c + 3, v.y.y, cnt);
+        }
+        for (; c < n; ++c) visit<T>(parent, ri, r, c, row[c], cnt);
     }
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
     __shared__ uint32_t part[kThreads / 64];
@@ -101,27 +146,28 @@ __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_count_roots(int32_t* parent, int32_t n, uint32_t* roots)
+// One workgroup: counts the roots of the forest, then writes the cost
+// model's inputs: log2 n, log10 density (clamped to 1e-9), log2 batch,
+// weakly connected (1 / 0; a graph of one vertex or none is connected).
+constexpr int kFinishThreads = 1024;
+__global__ __launch_bounds__(kFinishThreads) void k_features_finish(const int32_t* parent, int32_t n, int32_t batch,
+                                                                    const unsigned long long* edges, float* x)
 {
     uint32_t cnt = 0;
-    for (int32_t v = blockIdx.x * kThreads + threadIdx.x; v < n; v += gridDim.x * kThreads)
-        cnt += load_parent(parent, v) == v;
+    for (int32_t v = threadIdx.x; v < n; v += kFinishThreads) cnt += parent[v] == v;
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(roots, cnt);
-}
-
-// The cost model's inputs: log2 n, log10 density (clamped to 1e-9),
-// log2 batch, weakly connected (1 / 0).
-__global__ void k_features_final(int32_t n, int32_t batch, const unsigned long long* edges, const uint32_t* roots,
-                                 float* x)
-{
+    __shared__ uint32_t part[kFinishThreads / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    uint32_t roots = 0;
+    for (int w = 0; w < kFinishThreads / 64; ++w) roots += part[w];
     const double pairs = (double)n * (double)(n > 1 ? n - 1 : 1);
     const double dens = fmax((double)*edges / pairs, 1e-9);
     x[0] = (float)log2((double)(n > 1 ? n : 1));
     x[1] = (float)log10(dens);
     x[2] = (float)log2((double)(batch > 1 ? batch : 1));
-    x[3] = (n <= 1 || *roots == 1u) ? 1.f : 0.f;   // one vertex (or none) is connected
+    x[3] = (n <= 1 || roots == 1u) ? 1.f : 0.f;
 }
 
 }  // namespace
@@ -129,22 +175,18 @@ __global__ void k_features_final(int32_t n, int32_t batch, const unsigned long l
 hipError_t launch_graph_features(DType dt, const void* D, int32_t n, int64_t ld, int32_t* parent,
                                  unsigned long long* edges, uint32_t* roots, float* x, hipStream_t st)
 {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(edges), 0u, 2, st);
-    if (e == hipSuccess) e = launch_fill_u32(roots, 0u, 1, st);
-    if (e != hipSuccess) return e;
+    const int gi = (int)std::min<int64_t>(std::max<int64_t>((n + kThreads - 1) / kThreads, 1), 1024);
+    hipLaunchKernelGGL(k_features_init, dim3(gi), dim3(kThreads), 0, st, parent, n > 1 ? n : 0, edges, roots);
     if (n > 1) {
-        const int gi = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 1024);
         const int gr = (int)std::min<int64_t>(n, 4096);
-        hipLaunchKernelGGL(k_parent_init, dim3(gi), dim3(kThreads), 0, st, parent, n);
         if (dt == F32)
             hipLaunchKernelGGL(k_graph_edges<float>, dim3(gr), dim3(kThreads), 0, st, (const float*)D, n, ld, parent,
                                edges);
         else
             hipLaunchKernelGGL(k_graph_edges<uint32_t>, dim3(gr), dim3(kThreads), 0, st, (const uint32_t*)D, n, ld,
                                parent, edges);
-        hipLaunchKernelGGL(k_count_roots, dim3(gi), dim3(kThreads), 0, st, parent, n, roots);
     }
-    hipLaunchKernelGGL(k_features_final, dim3(1), dim3(64), 0, st, n, 1, edges, roots, x);
+    hipLaunchKernelGGL(k_features_finish, dim3(1), dim3(kFinishThreads), 0, st, parent, n > 1 ? n : 0, 1, edges, x);
     return hipGetLastError();
 }
 

@@ -60,6 +60,17 @@ def cases():
     np.fill_diagonal(star, 0)
     star[1:, 0] = 7           # every vertex points to 0
     out.append(("star_in", star))
+    # three dense random blocks with no edge between them, in a shuffled vertex order
+    blk = np.full((3001, 3001), INF, np.int32)
+    for a, b in ((0, 1000), (1000, 2200), (2200, 3001)):
+        blk[a:b, a:b] = np.where(rng.random((b - a, b - a)) < 0.05, rng.integers(1, 100, (b - a, b - a)), INF)
+    perm = rng.permutation(3001)
+    blk = blk[perm][:, perm]
+    np.fill_diagonal(blk, 0)
+    out.append(("three_blocks3001", np.ascontiguousarray(blk)))
+    big = np.where(rng.random((4096, 4096)) < 0.05, rng.integers(1, 100, (4096, 4096)), INF).astype(np.int32)
+    np.fill_diagonal(big, 0)
+    out.append(("rand4096_0.05", big))
     F = np.where(rng.random((500, 500)) < 0.004, rng.uniform(0.1, 10, (500, 500)), np.inf).astype(np.float32)
     np.fill_diagonal(F, 0)
     out.append(("f32_500", F))
@@ -74,6 +85,21 @@ def test_features_match_host(native, dev, name, W):
     assert got[1] == pytest.approx(want[1], abs=1e-5)
     assert got[2] == 0.0
     assert got[3] == want[3], f"{name}: connected flag"
+
+
+def test_features_strided_view(native, dev):
+    """A matrix inside a wider buffer (row stride n + 3, rows not 16-byte
+    aligned) gives the features of the matrix alone."""
+    rng = np.random.default_rng(78)
+    for n in (1027, 2050):
+        W = np.where(rng.random((n, n)) < 0.003, rng.integers(1, 100, (n, n)), INF).astype(np.int32)
+        np.fill_diagonal(W, 0)
+        buf = torch.zeros((n, n + 3), dtype=torch.int32, device=dev)   # zeros outside: would count as edges
+        buf[:, :n] = torch.from_numpy(W).to(dev)
+        got = native.apsp_features(buf[:, :n])
+        want = host_features(W)
+        assert got[1] == pytest.approx(want[1], abs=1e-5)
+        assert got[3] == want[3]
 
 
 def test_features_one_vertex(native, dev):
