@@ -153,9 +153,9 @@ def bench_int32_products(torch, apsp, Wd, n, cutover):
 
 
 def bench_small(torch, apsp, gg, dev):
-    """The smaller single-graph configurations: n = 256 (blocked FW, one
-    closure-sized graph), n = 4096 by blocked FW and by R-Kleene, whole-graph
-    squaring at both sizes, blocked FW with and without INF-slice skipping on
+    """The smaller single-graph configurations: n = 256 (blocked FW, squaring
+    in one launch, the default solve), n = 4096 by blocked FW and by R-Kleene,
+    whole-graph squaring at both sizes, blocked FW with and without INF-slice skipping on
     a very sparse n = 8192 graph, and the last-hop predecessors at n = 4096
     (dense argmin over n^3 terms, sparse form over n * m)."""
     out = {}
@@ -186,13 +186,15 @@ def bench_small(torch, apsp, gg, dev):
         nn = W.shape[0]
         t = per_solve(lambda d: apsp.apsp_square(d, **kw), W, reps)
         probe = W.clone()
-        apsp.apsp_profile_enable(True, kinds=[apsp.KERNEL_MINPLUS_128, apsp.KERNEL_MINPLUS_64])
         apsp.apsp_square(probe, **kw)
-        torch.cuda.synchronize()
-        passes = sum(apsp.apsp_profile_read(k)["launches"] for k in (apsp.KERNEL_MINPLUS_128, apsp.KERNEL_MINPLUS_64))
-        apsp.apsp_profile_enable(False)
+        passes = apsp.apsp_square_passes()
         out[label] = {"ms_per_solve": t * 1e3, "updates_per_s": nn ** 3 / t, "passes": passes,
-                      "terms_per_s": passes * nn ** 3 / t}
+                      "terms_per_s": passes * nn ** 3 / t,
+                      "form": "one launch" if nn <= 2048 and not kw else "one launch per pass"}
+    # the default solve at n = 256: device features, the model's pick, the solve
+    t = per_solve(lambda d: apsp.apsp_solve(d), W256, 100)
+    out["n256_default_solve_i32"] = {"ms_per_solve": t * 1e3, "updates_per_s": 256 ** 3 / t,
+                                     "candidate": apsp.apsp_solve_choice()}
     D4k = W4k.clone()
     apsp.apsp_fw(D4k)
     m = int(torch.count_nonzero(W4k < (1 << 30)).item()) - 4096

@@ -220,12 +220,27 @@ apsp_status_t apsp_rkleene(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
 
 /*
  * All-pairs shortest paths by repeated min-plus squaring (Sec. 3.2):
- * D <- min(D, D (min,+) D) until no entry changes (at most
- * ceil(log2(n-1)) + 1 passes).  Uses a 4-byte device flag in the context
- * scratch and synchronises `stream` once per pass to read it.
+ * D <- min(D, D (min,+) D) until a pass changes nothing, at most
+ * ceil(log2(n-1)) passes of change (by then every shortest path, of at most
+ * n - 1 edges, is covered).  For n <= 2048 without APSP_FLAG_PACKED16 or
+ * APSP_FLAG_SKIP_INF every pass runs inside one launch (tasks of a pass wait
+ * on the previous pass's counter in the context scratch; no host
+ * synchronisation); otherwise one launch per pass, and `stream` is
+ * synchronised once per pass to read the device "changed" flag.  Passes
+ * are in place (int32 exact; fp32 within rounding of the exact distances).
+ * apsp_square_passes reports the number of passes of the last call.
  */
 apsp_status_t apsp_square(apsp_ctx_t *ctx, apsp_dtype_t dtype, int64_t n,
                           void *D, int64_t ldd, const apsp_opts_t *opts, void *stream);
+
+/*
+ * Passes the last apsp_square call on this context ran: a pass that changes
+ * nothing ends the loop and is counted; the one-launch form also stops after
+ * ceil(log2(n-1)) passes (0 for n <= 2).  After a one-launch call this
+ * waits for `stream` (that call's stream) and reads the count from the
+ * device.  APSP_E_STATE if apsp_square has not run on the context.
+ */
+apsp_status_t apsp_square_passes(apsp_ctx_t *ctx, void *stream, int32_t *h_passes);
 
 /*
  * APSP_FLAG_PACKED16 (int32 only; other dtypes: APSP_E_UNSUPPORTED, and

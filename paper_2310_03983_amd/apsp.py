@@ -43,6 +43,7 @@ EXPORTS = [
     "apsp_workspace_size", "apsp_set_workspace", "apsp_path", "apsp_batched_noalloc",
     "apsp_features", "apsp_solve_choice", "apsp_batched_status",
     "apsp_batch_candidate_count", "apsp_batch_candidate", "apsp_plan_batch", "apsp_batched_choice",
+    "apsp_square_passes",
 ]
 # the trained cost model shipped with the package (plain-text model file)
 MODEL_PATH = os.path.join(_PKG, "data", "costmodel_mlp.txt")
@@ -146,6 +147,7 @@ def lib() -> ctypes.CDLL:
             L.apsp_path.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, i32, vp, vp]
             L.apsp_features.argtypes = [vp, i32, i64, vp, i64, vp, P(ctypes.c_float)]
             L.apsp_solve_choice.argtypes = [vp, P(i32)]
+            L.apsp_square_passes.argtypes = [vp, vp, P(i32)]
             L.apsp_batched_status.argtypes = [vp, vp, P(ctypes.c_uint32)]
             L.apsp_batch_candidate_count.argtypes = []
             L.apsp_batch_candidate.argtypes = [i32, P(Opts)]
@@ -457,6 +459,16 @@ def apsp_profile_read(kind: int, device: int | None = None) -> dict:
     st = KernelStats()
     _check(lib().apsp_profile_read(context(device), kind, ctypes.byref(st)))
     return {"launches": st.launches, "ms": st.milliseconds, "terms": st.terms, "bytes": st.bytes}
+
+
+def apsp_square_passes(device: int | None = None) -> int:
+    """Passes the last apsp_square on this device's context ran (waits for
+    torch's current stream after the one-launch form)."""
+    dev = torch.cuda.current_device() if device is None else device
+    p = ctypes.c_int32(0)
+    _check(lib().apsp_square_passes(context(dev), ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream),
+                                    ctypes.byref(p)))
+    return int(p.value)
 
 
 def apsp_packed16_counts(device: int | None = None) -> tuple[int, int]:

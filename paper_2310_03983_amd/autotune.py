@@ -1,9 +1,11 @@
 """Exhaustive autotuner and cost-model trainer.
 
     python -m paper_2310_03983_amd.autotune sweep --db timings.json [--first G0 --last G1]
+    python -m paper_2310_03983_amd.autotune retime --db timings.json --candidates 6 --max-n 2048
     python -m paper_2310_03983_amd.autotune train --db timings.json --model model.json
     python -m paper_2310_03983_amd.autotune evaluate --db timings.json --model model.json
     python -m paper_2310_03983_amd.autotune batch --db batch_timings.json
+    python -m paper_2310_03983_amd.autotune select-joint --db timings.json --batch-db batch_timings.json
     python -m paper_2310_03983_amd.autotune train-joint --db timings.json --batch-db batch_timings.json --model m.json
     python -m paper_2310_03983_amd.autotune evaluate-joint --db timings.json --batch-db batch_timings.json --model m.json
     python -m paper_2310_03983_amd.autotune export --model model.json --out model.txt
@@ -186,6 +188,34 @@ def sweep(db_path, first=0, last=199, progress=print):
     return db
 
 
+def retime(db_path, candidates, max_n, progress=print):
+    """Times the listed candidates again on every recorded sweep graph with
+    n <= max_n (after a change to their kernels) and replaces their entries;
+    each new result is compared bit for bit with candidate 0's."""
+    import torch
+    from . import apsp
+    dev = torch.device("cuda:0")
+    db = load_db(db_path)
+    if db.get("candidates") != candidate_table(apsp):
+        raise ValueError("the database was taken with another candidate table")
+    graphs = {sg.g: sg for sg in gg.sweep()}
+    for key, rec in sorted(db["records"].items(), key=lambda kv: int(kv[0])):
+        if rec["n"] > max_n:
+            continue
+        W = gg.sweep_graph_i32(graphs[int(key)])
+        Wd = torch.from_numpy(W).to(dev)
+        _, ref = time_candidate(torch, apsp, Wd, apsp.apsp_candidate(0))
+        for i in candidates:
+            t, D = time_candidate(torch, apsp, Wd, apsp.apsp_candidate(i))
+            rec["times"][i] = t
+            rec["agree"] = bool(rec["agree"] and torch.equal(ref, D))
+        save_db(db, db_path)
+        progress(f"[autotune] graph {key} n={rec['n']} retimed {candidates}: "
+                 f"{[round(rec['times'][i] * 1e3, 3) for i in candidates]} ms agree={rec['agree']}")
+        del Wd, ref
+    return db
+
+
 # ---------------------------------------------------------------------------
 # batched plans
 # ---------------------------------------------------------------------------
@@ -330,6 +360,27 @@ def train_joint(db, ids, bdb, bids, steps=4000, lr=3e-3, seed=0):
             "candidates": db["candidates"], "batch_candidates": bdb["candidates"], "train_ids": list(ids),
             "batch_train_ids": list(bids), "steps": steps, "lr": lr, "seed": seed,
             "loss_first": float(h[0]), "loss_last": float(h[-1])}
+
+
+def select_joint(db, bdb, grid=((4000, 8000), (3e-3, 1e-3), (0, 1, 2)), progress=print):
+    """Training settings of the joint model chosen by validation: each
+    (steps, lr, seed) is trained on sweep graphs 0-119 and the batch
+    training set without batches 100-119, and scored by the sum of the mean
+    regrets on graphs 120-149 and batches 100-119; the best is returned (the
+    held-out test graphs 150-199 and batches 120-159 are not looked at)."""
+    btr = [b for b in BATCH_TRAIN if not (100 <= b < 120)]
+    bval = list(range(100, 120))
+    res = []
+    for steps in grid[0]:
+        for lr in grid[1]:
+            for seed in grid[2]:
+                m = train_joint(db, list(range(120)), bdb, btr, steps=steps, lr=lr, seed=seed)
+                es = evaluate(db, m, list(range(120, 150)), list(range(120)))["mlp"]["mean_regret"]
+                eb = evaluate_batches(bdb, m, bval, btr)["mlp"]["mean_regret"]
+                res.append((es + eb, steps, lr, seed))
+                progress(f"[autotune] steps={steps} lr={lr} seed={seed}: validation regret {es:.4f} + {eb:.4f}")
+    _, steps, lr, seed = min(res)
+    return {"steps": steps, "lr": lr, "seed": seed}
 
 
 def forward(model, X):
@@ -491,8 +542,10 @@ def evaluate(db, model, test_ids, train_ids):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["sweep", "train", "evaluate", "batch", "export", "train-joint",
-                                    "evaluate-joint"])
+    ap.add_argument("cmd", choices=["sweep", "retime", "train", "evaluate", "batch", "export", "select-joint",
+                                    "train-joint", "evaluate-joint"])
+    ap.add_argument("--candidates", default="6", help="retime: comma-separated candidate indices")
+    ap.add_argument("--max-n", type=int, default=2048, help="retime: largest n re-timed")
     ap.add_argument("--batch-db", help="batch timing database (batch, train-joint, evaluate-joint)")
 
     ap.add_argument("--out", help="export: path of the text model file")
@@ -501,7 +554,9 @@ def main(argv=None):
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--last", type=int, default=199)
     ap.add_argument("--train-count", type=int, default=150)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=None, help="Adam steps (train: 3000; train-joint: 8000)")
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--seed", type=int, default=2, help="train-joint: initialisation seed")
     a = ap.parse_args(argv)
     if a.cmd == "export":
         with open(a.model) as f:
@@ -512,17 +567,23 @@ def main(argv=None):
     if a.cmd == "sweep":
         sweep(a.db, a.first, a.last, progress=lambda m: print(m, flush=True))
         return 0
+    if a.cmd == "retime":
+        retime(a.db, [int(c) for c in a.candidates.split(",")], a.max_n, progress=lambda m: print(m, flush=True))
+        return 0
     if a.cmd == "batch":
         sweep_batches(a.db, a.first, a.last, progress=lambda m: print(m, flush=True))
         return 0
     db = load_db(a.db)
     train_ids = list(range(a.train_count))
     test_ids = list(range(a.train_count, 200))
-    if a.cmd in ("train-joint", "evaluate-joint"):
+    if a.cmd in ("select-joint", "train-joint", "evaluate-joint"):
         bdb = load_db(a.batch_db)
         btrain, btest = BATCH_TRAIN, BATCH_TEST
+        if a.cmd == "select-joint":
+            print(json.dumps(select_joint(db, bdb, progress=lambda m: print(m, flush=True))))
+            return 0
         if a.cmd == "train-joint":
-            model = train_joint(db, train_ids, bdb, btrain, steps=a.steps)
+            model = train_joint(db, train_ids, bdb, btrain, steps=a.steps or 8000, lr=a.lr, seed=a.seed)
             with open(a.model, "w") as f:
                 json.dump(model, f)
             print(json.dumps({k: model[k] for k in ("K", "loss_first", "loss_last", "steps")}))
@@ -533,7 +594,7 @@ def main(argv=None):
                           "batch": evaluate_batches(bdb, model, btest, btrain)}, indent=1))
         return 0
     if a.cmd == "train":
-        model = train(db, train_ids, steps=a.steps)
+        model = train(db, train_ids, steps=a.steps or 3000)
         with open(a.model, "w") as f:
             json.dump(model, f)
         print(json.dumps({k: model[k] for k in ("K", "loss_first", "loss_last", "steps")}))

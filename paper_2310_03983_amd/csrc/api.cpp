@@ -80,6 +80,9 @@ struct apsp_ctx {
     float* cm_grad = nullptr;
     float* cm_ws = nullptr;         // activation workspace for kCmMaxRows rows
     float* cm_io = nullptr;         // plan: 4 features, K outputs, 1 choice
+    float* h_io = nullptr;          // pinned host copy of the plan read-back (4 KB)
+    int32_t square_passes = -1;     // passes of the last apsp_square (host-driven form)
+    bool square_passes_device = false;   // ... or in the scratch (one-launch form)
     int32_t cm_steps = 0;           // Adam steps taken since init / set_params
     apsp::MlpNorm cm_norm{};
     bool prof = false;              // kernel timing enabled
@@ -519,10 +522,29 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld)
     return (size_t)(((rows - 1) * ld + cols) * 4);
 }
 
+// Squaring runs as one launch up to this size (its passes are latency-bound
+// there); larger graphs take one launch and one flag read-back per pass.
+constexpr int64_t kCoopSquareMaxN = 2048;
+constexpr int kSquarePassesWord = 50;   // in the synchronisation block below
+// tickets, pass counters, flags and pass count of the one-launch squaring
+// (scratch bytes 256 .. 511)
+uint32_t* square_sync(apsp_ctx_t* ctx) { return static_cast<uint32_t*>(ctx->d_scratch) + 64; }
+
 apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int64_t ld,
                             const Plan& pl, hipStream_t st)
 {
     if (n <= 1) return APSP_OK;
+    if (!pl.p16 && !pl.skip && n <= kCoopSquareMaxN) {
+        // small graph: every pass in one launch, no read-back
+        if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
+        ctx->square_passes = 0;
+        ctx->square_passes_device = n > 2;
+        return timed(ctx, APSP_KERNEL_OTHER, 0.0, 0.0, st, [&]() -> apsp_status_t {
+            HIP_TRY(apsp::launch_square_flow((apsp::DType)dt, D, (int)n, ld, square_sync(ctx), ctx->num_cus, st),
+                    "squaring launch");
+            return APSP_OK;
+        });
+    }
     uint32_t* flag = static_cast<uint32_t*>(ctx->d_scratch) + 4;
     int passes = 0;
     apsp_status_t rc;
@@ -542,6 +564,8 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
         HIP_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st), "flag copy");
         HIP_TRY(hipStreamSynchronize(st), "flag sync");
         ++passes;
+        ctx->square_passes = passes;
+        ctx->square_passes_device = false;
         if (!h) break;
         if (passes > 64) return fail(APSP_E_INPUT, "squaring did not converge (negative costs?)");
     }
@@ -851,11 +875,11 @@ apsp_status_t plan_matrix(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, const voi
                                         feat_edges(ctx), feat_roots(ctx), x, st),
             "feature pass");
     HIP_TRY(apsp::launch_mlp_forward(ctx->cm_params, ctx->cm_norm, x, 1, K, ctx->cm_ws, x + 4, st), "mlp forward");
-    std::vector<float> h(4 + K);
-    HIP_TRY(hipMemcpyAsync(h.data(), x, h.size() * sizeof(float), hipMemcpyDeviceToHost, st), "plan read-back");
+    float* h = ctx->h_io;   // pinned; 4 + K <= 1024 floats
+    HIP_TRY(hipMemcpyAsync(h, x, (4 + K) * sizeof(float), hipMemcpyDeviceToHost, st), "plan read-back");
     HIP_TRY(hipStreamSynchronize(st), "plan sync");
-    if (h_x) std::copy(h.begin(), h.begin() + 4, h_x);
-    *h_choice = pick_candidate(dt, h.data() + 4);
+    if (h_x) std::copy(h, h + 4, h_x);
+    *h_choice = pick_candidate(dt, h + 4);
     return APSP_OK;
 }
 
@@ -925,6 +949,18 @@ apsp_status_t apsp_create(apsp_ctx_t** out, int32_t device)
         delete c;
         return fail(APSP_E_NOMEM, "scratch allocation: %s", hipGetErrorString(e));
     }
+    // pinned, so that the plan read-back is one direct copy
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->h_io), 4096, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipFree(c->d_scratch);
+        hipStreamDestroy(c->capture);
+        hipStreamDestroy(c->side);
+        hipEventDestroy(c->ev_a);
+        hipEventDestroy(c->ev_p);
+        hipEventDestroy(c->ev_b);
+        delete c;
+        return fail(APSP_E_NOMEM, "pinned host buffer: %s", hipGetErrorString(e));
+    }
     *out = c;
     return APSP_OK;
 }
@@ -936,6 +972,7 @@ apsp_status_t apsp_destroy(apsp_ctx_t* ctx)
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
     if (ctx->d_scratch) hipFree(ctx->d_scratch);
+    if (ctx->h_io) hipHostFree(ctx->h_io);
     for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
     free_costmodel(ctx);
     drop_batch_graphs(ctx);
@@ -1087,6 +1124,25 @@ apsp_status_t apsp_square(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, 
         pl.p16 = false;
         return square_common(ctx, dt, n, D, ldd, pl, st);
     });
+}
+
+apsp_status_t apsp_square_passes(apsp_ctx_t* ctx, void* stream, int32_t* h_passes)
+{
+    apsp_status_t rc;
+    if (!h_passes) return fail(APSP_E_ARG, "h_passes is NULL");
+    if ((rc = check_ctx(ctx))) return rc;
+    if (ctx->square_passes < 0) return fail(APSP_E_STATE, "apsp_square has not run on this context");
+    if (!ctx->square_passes_device) {
+        *h_passes = ctx->square_passes;
+        return APSP_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(ctx->h_io, square_sync(ctx) + kSquarePassesWord, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           st),
+            "pass count read-back");
+    HIP_TRY(hipStreamSynchronize(st), "pass count sync");
+    *h_passes = (int32_t)reinterpret_cast<const uint32_t*>(ctx->h_io)[0];
+    return APSP_OK;
 }
 
 apsp_status_t apsp_packed16_counts(apsp_ctx_t* ctx, int64_t* runs, int64_t* redone)

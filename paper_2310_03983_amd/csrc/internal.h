@@ -95,6 +95,14 @@ hipError_t launch_fold_spin(DType dt, int grid, int iters, uint32_t seed, uint32
 hipError_t launch_square_pass(DType dt, int tile, void* D, int64_t n, int64_t ld,
                               uint32_t* d_changed, bool skip, hipStream_t st);
 
+// Whole-graph squaring of an n x n int32 or fp32 matrix in one launch (n
+// small enough that the passes are latency-bound); sync: the
+// kSquareSyncWords words of tickets, pass counters and flags (zeroed here by
+// a fill kernel); sync[49] receives an error bit if a wait overran and
+// sync[50] the number of passes run.
+constexpr int kSquareSyncWords = 64;
+hipError_t launch_square_flow(DType dt, void* D, int n, int64_t ld, uint32_t* sync, int num_cus, hipStream_t st);
+
 // Ragged batch: graph g is the n x n row-major matrix at data + offsets[g]
 // (elements), n = sizes[g].  Workgroups take graphs in the order order[0..count).
 struct BatchArgs {

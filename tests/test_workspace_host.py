@@ -74,6 +74,10 @@ assert L.apsp_path(c, 10, fake, 10, 1, fake, fake, fake, 0, fake, None) == a.APS
 assert L.apsp_path(c, 10, fake, 10, 1, None, fake, fake, 10, fake, None) == a.APSP_E_ARG
 assert L.apsp_path(c, 10, fake, 9, 1, fake, fake, fake, 10, fake, None) == a.APSP_E_ARG
 assert L.apsp_path(c, 10, fake, 10, 0, None, None, None, 10, None, None) == 0
+# squaring pass count: nothing to report before the first apsp_square
+npass = ctypes.c_int32(7)
+assert L.apsp_square_passes(c, None, ctypes.byref(npass)) == a.APSP_E_STATE
+assert L.apsp_square_passes(c, None, None) == a.APSP_E_ARG
 print("host workspace checks ok", need)
 """
 
