@@ -95,6 +95,8 @@ typedef int32_t apsp_dtype_t;
 #define APSP_FLAG_BATCH_QUEUE      128 /* apsp_batched: dependency-driven schedule, one workgroup per task
                                           (see apsp_batched) */
 #define APSP_FLAG_BATCH_LOCKSTEP   256 /* apsp_batched: the lock-step schedule (see apsp_batched) */
+#define APSP_FLAG_BATCH_GLOBAL     512 /* apsp_batched with APSP_FLAG_BATCH_QUEUE: one ticket queue for the
+                                          whole device instead of one per XCD (see apsp_batched) */
 #define APSP_FLAG_SKIP_INF         64 /* minplus_gemm / apsp_fw / apsp_rkleene / apsp_square / apsp_solve:
                                          a product skips every reduction slice (16 or 32 steps of one
                                          tile) whose A block or B block is all INF -- exact, since
@@ -357,17 +359,21 @@ apsp_status_t apsp_path(apsp_ctx_t *ctx, int64_t n, const int32_t *P, int64_t ld
  * element offset of graph g and d_sizes[g] (int32, device) its n; h_sizes is
  * the same sizes on the host (used to plan, never dereferenced on device).
  * Every matrix is overwritten with its distances (Sec. 2, Eq. 1 per graph,
- * blocked into rounds).  n <= 1024 per graph (APSP_E_UNSUPPORTED beyond:
- * use apsp_solve).
+ * blocked into rounds).  n <= 1024 per graph for the lock-step and
+ * persistent schedules, n <= 8192 for the queue schedule (APSP_E_UNSUPPORTED
+ * beyond: use apsp_solve).
  *
  * Plan.  With every option automatic (opts NULL or all fields 0) the cost
  * model picks one of the batch candidates (apsp_batch_candidate) from the
  * batch's features (apsp_plan_batch; the density is counted on the device
  * and read back, so the first call with a new batch shape synchronises
  * `stream`); without a model with batch outputs the default candidate runs
- * (the queue schedule with 64 x 64 sub-tiles for n > 128).  The plan is made
- * once per batch shape (apsp_batched_choice reports it).  Otherwise the flags
- * select the schedule:
+ * (the queue schedule with 64 x 64 sub-tiles for n > 128).  A batch with a
+ * graph above n = 1024 takes the best-scored queue candidate, and a batch of
+ * fewer graphs than the device has XCDs takes it with
+ * APSP_FLAG_BATCH_GLOBAL.  The plan is made once per batch shape
+ * (apsp_batched_choice reports the candidate).  Otherwise the flags select
+ * the schedule:
  *
  * APSP_FLAG_BATCH_QUEUE: a dependency-driven schedule in one launch: every
  * graph's first pivot closure, panel tiles, remainder tiles and next pivots
@@ -381,7 +387,9 @@ apsp_status_t apsp_path(apsp_ctx_t *ctx, int64_t n, const int32_t *P, int64_t ld
  * with n > opts->reserved[0] (all when 0) take round width opts->block
  * (64 or 128; 0 = 128) and, with opts->tile = APSP_TILE_64 and 128-wide
  * rounds, products cut into 64 x 64 sub-tile tasks; the others take 128-wide
- * rounds of whole tiles.
+ * rounds of whole tiles.  With APSP_FLAG_BATCH_GLOBAL all tasks share one
+ * queue, so one graph's tasks spread over every XCD; a task then writes its
+ * tile back beyond its XCD's L2 (an agent-scope release) before it signals.
  *
  * APSP_FLAG_BATCH_LOCKSTEP: all graphs advance one 128-wide round per launch
  * group -- the panel tiles of every graph, then the next round's pivot tiles

@@ -28,6 +28,7 @@ FLAG_PACKED16 = 32
 FLAG_SKIP_INF = 64
 FLAG_BATCH_QUEUE = 128
 FLAG_BATCH_LOCKSTEP = 256
+FLAG_BATCH_GLOBAL = 512
 CAP16 = 0x39FF    # 14847: cap of the APSP_FLAG_PACKED16 products
 
 # every symbol include/apsp.h declares
@@ -79,7 +80,8 @@ class KernelStats(ctypes.Structure):
 
 def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True,
               batch_graph=True, batch_per_graph=False, lookahead=True, batch_persistent=False,
-              packed16=False, skip_inf=False, batch_queue=False, batch_lockstep=False) -> Opts:
+              packed16=False, skip_inf=False, batch_queue=False, batch_lockstep=False,
+              batch_global=False) -> Opts:
     o = Opts()
     o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
     o.block = int(block)
@@ -90,7 +92,7 @@ def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, spli
         (FLAG_BATCH_PER_GRAPH if batch_per_graph else 0) | (0 if lookahead else FLAG_NO_LOOKAHEAD) | \
         (FLAG_BATCH_PERSISTENT if batch_persistent else 0) | (FLAG_PACKED16 if packed16 else 0) | \
         (FLAG_SKIP_INF if skip_inf else 0) | (FLAG_BATCH_QUEUE if batch_queue else 0) | \
-        (FLAG_BATCH_LOCKSTEP if batch_lockstep else 0)
+        (FLAG_BATCH_LOCKSTEP if batch_lockstep else 0) | (FLAG_BATCH_GLOBAL if batch_global else 0)
     return o
 
 

@@ -996,10 +996,13 @@ size_t apsp_workspace_size(apsp_ctx_t* ctx, int32_t op, apsp_dtype_t dt, int64_t
     switch (op) {
     case APSP_OP_SOLVE: return n_or_total > 1 ? solve_ws_bytes(n_or_total) : 0;
     case APSP_OP_BATCHED: {
-        const int64_t max_n = std::min<int64_t>(n_or_total, apsp::batched_max_n());
-        const int32_t nb = (int32_t)queue_rounds_bound((int)std::max<int64_t>(max_n, 1));
-        return batch_layout(count, (size_t)count * batched_items_bound((int)std::max<int64_t>(max_n, 1)),
-                            (size_t)count * batched_tasks_bound((int)std::max<int64_t>(max_n, 1)),
+        // lock-step items up to the lock-step limit, queue tasks and counters
+        // up to the queue limit
+        const int items_n = (int)std::max<int64_t>(std::min<int64_t>(n_or_total, apsp::batched_max_n()), 1);
+        const int queue_n = (int)std::max<int64_t>(std::min<int64_t>(n_or_total, apsp::kQueueMaxN), 1);
+        const int32_t nb = (int32_t)queue_rounds_bound(queue_n);
+        return batch_layout(count, (size_t)count * batched_items_bound(items_n),
+                            (size_t)count * batched_tasks_bound(queue_n),
                             count * (nb >= 2 ? 4 * nb : 0) + kMaxXcds * (int32_t)(kWsAlign / sizeof(int32_t)))
             .bytes;
     }
@@ -1357,17 +1360,21 @@ void batch_features(int32_t count, const int32_t* h_sizes, double density, float
 
 // First minimum of the batch candidates' predicted scores (outputs
 // kNumCandidates ..).
-int32_t pick_batch_candidate(const float* pred)
+bool batch_candidate_is_queue(int32_t i) { return (kBatchCandidates[i].flags & APSP_FLAG_BATCH_QUEUE) != 0; }
+
+// The best-scored batch candidate; queue candidates only when a graph is
+// above the lock-step and persistent limit.
+int32_t pick_batch_candidate(const float* pred, bool queue_only)
 {
-    int32_t choice = 0;
-    for (int32_t i = 1; i < kNumBatchCandidates; ++i)
-        if (pred[i] < pred[choice]) choice = i;
+    int32_t choice = -1;
+    for (int32_t i = 0; i < kNumBatchCandidates; ++i)
+        if ((!queue_only || batch_candidate_is_queue(i)) && (choice < 0 || pred[i] < pred[choice])) choice = i;
     return choice;
 }
 
 // Scores the batch candidates for features x (device forward pass, one
 // read-back).
-apsp_status_t score_batch(apsp_ctx_t* ctx, const float* x, hipStream_t st, int32_t* choice)
+apsp_status_t score_batch(apsp_ctx_t* ctx, const float* x, bool queue_only, hipStream_t st, int32_t* choice)
 {
     const int K = ctx->cm_K;
     HIP_TRY(hipMemcpyAsync(ctx->cm_io, x, 4 * sizeof(float), hipMemcpyHostToDevice, st), "plan features upload");
@@ -1376,7 +1383,7 @@ apsp_status_t score_batch(apsp_ctx_t* ctx, const float* x, hipStream_t st, int32
     std::vector<float> h(K);
     HIP_TRY(hipMemcpyAsync(h.data(), ctx->cm_io + 4, K * sizeof(float), hipMemcpyDeviceToHost, st), "scores read-back");
     HIP_TRY(hipStreamSynchronize(st), "plan sync");
-    *choice = pick_batch_candidate(h.data() + kNumCandidates);
+    *choice = pick_batch_candidate(h.data() + kNumCandidates, queue_only);
     return APSP_OK;
 }
 
@@ -1387,12 +1394,14 @@ apsp_status_t batch_auto_plan(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, c
                               const int64_t* d_offsets, const int32_t* d_sizes, const int32_t* h_sizes,
                               hipStream_t st, apsp_opts_t* out)
 {
+    int32_t max_n = 0;
+    for (int32_t g = 0; g < count; ++g) max_n = std::max(max_n, h_sizes[g]);
     uint64_t key = 0xcbf29ce484222325ull ^ (uint64_t)dt;
     for (int32_t g = 0; g < count; ++g) key = (key ^ (uint64_t)(uint32_t)h_sizes[g]) * 1099511628211ull;
     key = (key ^ (uint64_t)count) * 1099511628211ull;
     key ^= batch_model_ready(ctx) ? 0x9e3779b97f4a7c15ull : 0;
     if (key != ctx->bauto_key || ctx->bauto_choice < 0) {
-        int32_t choice = kDefaultBatchCandidate;
+        int32_t choice = kDefaultBatchCandidate;   // a queue candidate
         if (batch_model_ready(ctx)) {
             auto* tot = reinterpret_cast<unsigned long long*>(static_cast<char*>(ctx->d_scratch) + 224);
             HIP_TRY(apsp::launch_batch_edges((apsp::DType)dt, data, d_offsets, d_sizes, count, tot, st),
@@ -1404,13 +1413,15 @@ apsp_status_t batch_auto_plan(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, c
             for (int32_t g = 0; g < count; ++g) pairs += (double)h_sizes[g] * std::max(h_sizes[g] - 1, 0);
             float x[4];
             batch_features(count, h_sizes, pairs > 0.0 ? (double)m / pairs : 0.0, x);
-            apsp_status_t rc = score_batch(ctx, x, st, &choice);
+            apsp_status_t rc = score_batch(ctx, x, max_n > apsp::batched_max_n(), st, &choice);
             if (rc) return rc;
         }
         ctx->bauto_key = key;
         ctx->bauto_choice = choice;
     }
     batch_candidate_opts(ctx->bauto_choice, out);
+    // fewer graphs than XCDs: one queue for the device, so every XCD works
+    if ((out->flags & APSP_FLAG_BATCH_QUEUE) && count < num_xcds(ctx)) out->flags |= APSP_FLAG_BATCH_GLOBAL;
     return APSP_OK;
 }
 
@@ -1431,12 +1442,18 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
     if (count < 0) return fail(APSP_E_ARG, "count = %d is negative", count);
     if (count > 0 && (!data || !d_offsets || !d_sizes || !h_sizes))
         return fail(APSP_E_ARG, "NULL batch pointer");
+    int32_t max_n = 0;
     for (int32_t g = 0; g < count; ++g) {
         if (h_sizes[g] < 0) return fail(APSP_E_ARG, "graph %d has n = %d", g, h_sizes[g]);
-        if (h_sizes[g] > apsp::batched_max_n())
-            return fail(APSP_E_UNSUPPORTED, "graph %d has n = %d > %d (use apsp_solve)", g, h_sizes[g],
-                        apsp::batched_max_n());
+        max_n = std::max(max_n, h_sizes[g]);
     }
+    // the lock-step and persistent schedules take n <= batched_max_n, the
+    // queue schedule n <= kQueueMaxN (the automatic plan then picks a queue)
+    const bool queue_asked = (o->flags & APSP_FLAG_BATCH_QUEUE) &&
+                             !(o->flags & (APSP_FLAG_BATCH_PERSISTENT | APSP_FLAG_BATCH_PER_GRAPH));
+    const int32_t limit = (queue_asked || opts_all_auto(o)) ? apsp::kQueueMaxN : apsp::batched_max_n();
+    if (max_n > limit)
+        return fail(APSP_E_UNSUPPORTED, "a graph has n = %d > %d for this schedule (use apsp_solve)", max_n, limit);
     if ((rc = check_ctx(ctx))) return rc;
     if (count == 0) return APSP_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1456,6 +1473,12 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
     key = (key ^ (uint64_t)(uint32_t)o->block) * 1099511628211ull;
     key = (key ^ (uint64_t)(uint32_t)o->reserved[0]) * 1099511628211ull;
     key = (key ^ (uint64_t)(uint32_t)o->tile) * 1099511628211ull;
+    constexpr int32_t kScheduleFlags = APSP_FLAG_BATCH_QUEUE | APSP_FLAG_BATCH_LOCKSTEP | APSP_FLAG_BATCH_PERSISTENT |
+                                       APSP_FLAG_BATCH_PER_GRAPH | APSP_FLAG_BATCH_GLOBAL;
+    key = (key ^ (uint64_t)(uint32_t)(o->flags & kScheduleFlags)) * 1099511628211ull;
+    const bool use_queue = (o->flags & APSP_FLAG_BATCH_QUEUE) &&
+                           !(o->flags & (APSP_FLAG_BATCH_PERSISTENT | APSP_FLAG_BATCH_PER_GRAPH));
+    const bool use_lockstep = !use_queue && !(o->flags & (APSP_FLAG_BATCH_PERSISTENT | APSP_FLAG_BATCH_PER_GRAPH));
     const bool rebuild = key != ctx->bkey || count != ctx->bcount || dt != ctx->bdtype;
     std::vector<int32_t> order;
     std::vector<int4> items;
@@ -1487,7 +1510,7 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
             const int cnt = (int)items.size() - start;
             if (cnt > 0) launches.push_back({phase, start, cnt, side});
         };
-        for (int r = 0; r < max_rounds; ++r) {
+        for (int r = 0; r < (use_lockstep ? max_rounds : 0); ++r) {
             if (r == 0)
                 add(0, false, [&](int32_t g, int) { items.push_back(make_int4(g, 0, 0, 0)); });
             add(1, false, [&](int32_t g, int nb) {
@@ -1514,15 +1537,18 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
                     }
             });
         }
-        std::vector<int32_t> widths(count), subs(count);
-        for (int32_t g = 0; g < count; ++g) {
-            widths[g] = queue_width(o, h_sizes[g]);
-            subs[g] = queue_sub(o, h_sizes[g]);
+        if (use_queue) {
+            std::vector<int32_t> widths(count), subs(count);
+            for (int32_t g = 0; g < count; ++g) {
+                widths[g] = queue_width(o, h_sizes[g]);
+                subs[g] = queue_sub(o, h_sizes[g]);
+            }
+            // one queue per XCD, or one for the device
+            const int nx = (o->flags & APSP_FLAG_BATCH_GLOBAL) ? 1 : num_xcds(ctx);
+            apsp::build_xcd_queues(widths.data(), subs.data(), count, h_sizes, order, nx,
+                                   (ctx->num_cus / nx) * apsp::batch_queue_resident_per_cu((apsp::DType)dt),
+                                   kWsAlign / (int)sizeof(int32_t), apsp::TaskCost{}, qtasks, qoff, qcounters);
         }
-        const int nx = num_xcds(ctx);
-        apsp::build_xcd_queues(widths.data(), subs.data(), count, h_sizes, order, nx,
-                               (ctx->num_cus / nx) * apsp::batch_queue_resident_per_cu((apsp::DType)dt),
-                               kWsAlign / (int)sizeof(int32_t), apsp::TaskCost{}, qtasks, qoff, qcounters);
     }
     // plan memory: [pointer record][ticket, error word][order][items][tasks]
     // [counters], in the caller's workspace or in the fixed scratch (after
@@ -1621,9 +1647,11 @@ apsp_status_t batched_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, vo
         int qmax = 0;
         for (int x = 0; x < nx; ++x) qmax = std::max(qmax, ctx->qoff[x + 1] - ctx->qoff[x]);
         const int ncnt = ctx->qcounters;
+        // one queue on a device of several XCDs: tasks release their tiles device-wide
+        const bool global = nx == 1 && num_xcds(ctx) > 1;
         auto enqueue = [&](hipStream_t s2) -> hipError_t {
             return apsp::launch_batch_queue(kdt, d_bptrs, d_tasks, d_qoff, nx, qmax, d_ticket, d_counters, ncnt, d_err,
-                                            s2);
+                                            global, s2);
         };
         return timed(ctx, APSP_KERNEL_OTHER, terms, bytes, st, [&]() -> apsp_status_t {
             HIP_TRY(apsp::launch_batch_ptrs(d_bptrs, data, d_offsets, d_sizes, st), "batch pointer update");
@@ -1898,13 +1926,17 @@ apsp_status_t apsp_plan_batch(apsp_ctx_t* ctx, apsp_dtype_t dt, int32_t count, c
     if ((rc = check_ctx(ctx))) return rc;
     int32_t choice = kDefaultBatchCandidate;
     if (h_choice) *h_choice = -1;
+    int32_t max_n = 0;
+    for (int32_t g = 0; g < count; ++g) max_n = std::max(max_n, h_sizes[g]);
     if (batch_model_ready(ctx)) {
         float x[4];
         batch_features(count, h_sizes, density, x);
-        if ((rc = score_batch(ctx, x, nullptr, &choice))) return rc;
+        if ((rc = score_batch(ctx, x, max_n > apsp::batched_max_n(), nullptr, &choice))) return rc;
         if (h_choice) *h_choice = choice;
     }
     batch_candidate_opts(choice, out);
+    // as apsp_batched's automatic plan: one queue for a batch of fewer graphs than XCDs
+    if ((out->flags & APSP_FLAG_BATCH_QUEUE) && count < num_xcds(ctx)) out->flags |= APSP_FLAG_BATCH_GLOBAL;
     return APSP_OK;
 }
 

@@ -250,6 +250,10 @@ __global__ __launch_bounds__(dev::kCloseWideThreads) void k_bpivot(const BatchPt
 // records the overrun in the error word and runs the task anyway, so every
 // launch ends.  The grid holds qlen_max workgroups per XCD (workgroups are
 // dispatched to the XCDs in turn); a workgroup whose queue is empty returns.
+// Global mode (one queue, nxcd = 1, for batches of a few large graphs): any
+// workgroup takes the next ticket, a graph's tasks run on every XCD, and a
+// producer writes its stores back beyond its L2 (agent-scope release)
+// before it signals.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr int kTicketStride = 64;   // one 256-byte slot per XCD queue
@@ -272,7 +276,7 @@ __device__ __forceinline__ void wait_counter(int32_t* c, int32_t need, uint32_t*
 template <class S>
 __global__ __launch_bounds__(dev::kCloseWideThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_bqueue(const BatchPtrs* __restrict__ bp, const BatchTask* __restrict__ tasks, const int32_t* __restrict__ qoff,
-              int nxcd, uint32_t* tickets, int32_t* counters, uint32_t* err)
+              int nxcd, uint32_t* tickets, int32_t* counters, uint32_t* err, int global)
 {
     using T = typename S::T;
     using P = typename S::P;
@@ -366,8 +370,12 @@ void k_bqueue(const BatchPtrs* __restrict__ bp, const BatchTask* __restrict__ ta
     }
     __builtin_amdgcn_s_waitcnt(0);   // this lane's stores have reached the L2
     __syncthreads();                   // ... and every lane's
-    if (tid == 0 && t.signal >= 0)
+    if (tid == 0 && t.signal >= 0) {
+        // one queue for the device: consumers may run on another XCD, so
+        // the tile leaves this XCD's L2 before the counter moves
+        if (global) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(counters + t.signal, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Edges of every graph of a batch (finite off-diagonal entries), summed into
@@ -470,7 +478,7 @@ hipError_t launch_batch_phase(DType dt, int phase, const BatchPtrs* bp, const in
 
 hipError_t launch_batch_queue(DType dt, const BatchPtrs* bp, const BatchTask* tasks, const int32_t* qoff, int nxcd,
                               int qlen_max, uint32_t* tickets, int32_t* counters, int ncounters, uint32_t* err,
-                              hipStream_t st)
+                              bool global, hipStream_t st)
 {
     if (qlen_max <= 0) return hipSuccess;
     // tickets and counters start at zero on every launch (fill kernels, so
@@ -481,10 +489,10 @@ hipError_t launch_batch_queue(DType dt, const BatchPtrs* bp, const BatchTask* ta
     const unsigned grid = (unsigned)nxcd * (unsigned)qlen_max;
     if (dt == I32)
         hipLaunchKernelGGL(k_bqueue<dev::SemI32>, dim3(grid), dim3(dev::kCloseWideThreads), 0, st, bp, tasks, qoff,
-                           nxcd, tickets, counters, err);
+                           nxcd, tickets, counters, err, global ? 1 : 0);
     else
         hipLaunchKernelGGL(k_bqueue<dev::SemF32>, dim3(grid), dim3(dev::kCloseWideThreads), 0, st, bp, tasks, qoff,
-                           nxcd, tickets, counters, err);
+                           nxcd, tickets, counters, err, global ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -132,10 +132,12 @@ int batched_round_width();
 
 // Zeroes the per-XCD tickets and counters[0..ncounters), then launches
 // nxcd * qlen_max workgroups; queue x holds tasks[qoff[x] .. qoff[x+1]);
-// *err gets bit 0 if a wait overran.
+// *err gets bit 0 if a wait overran.  global: the tasks of one queue run on
+// every XCD (nxcd = 1 on a device with several), so each task releases its
+// stores at agent scope before it signals.
 hipError_t launch_batch_queue(DType dt, const BatchPtrs* bp, const BatchTask* tasks, const int32_t* qoff, int nxcd,
                               int qlen_max, uint32_t* tickets, int32_t* counters, int ncounters, uint32_t* err,
-                              hipStream_t st);
+                              bool global, hipStream_t st);
 // Finite off-diagonal entries of every graph of a batch, summed into *total
 // (uint64, zeroed first).
 hipError_t launch_batch_edges(DType dt, const void* data, const int64_t* offsets, const int32_t* sizes, int count,
@@ -148,7 +150,8 @@ int batch_queue_resident_per_cu(DType dt);
 hipError_t launch_batched(DType dt, const BatchArgs& a, int grid, hipStream_t st);
 int batched_resident_per_cu(DType dt);
 const void* batched_kernel(DType dt);
-int batched_max_n();
+int batched_max_n();        // lock-step and persistent schedules
+constexpr int kQueueMaxN = 8192;   // queue schedule
 
 // ---- last-hop predecessors (pred.hip)
 // Sparse last-hop predecessors: column ranges of 1024, edges packed as

@@ -119,12 +119,48 @@ def test_batched_workload_512(native, dev, sched):
         np.testing.assert_array_equal(g, oracle.fw_i32(W, threads=8), err_msg=f"graph {b.g} n={b.n}")
 
 
-def test_batched_rejects_large_graph(native, dev):
+def test_batched_size_limits(native, dev):
+    """The lock-step and persistent schedules take n <= 1024, the queue
+    schedule (and the automatic plan, which then picks a queue) n <= 8192."""
     W = np.zeros((1025, 1025), np.int32)
     flat, off_d, sz_d, hs, off = pack([W], dev)
+    for kw in ({"batch_lockstep": True}, {"batch_persistent": True}):
+        with pytest.raises(native.ApspError) as e:
+            native.apsp_batched(flat, off_d, sz_d, hs, **kw)
+        assert e.value.status == native.APSP_E_UNSUPPORTED
+    native.apsp_batched(flat, off_d, sz_d, hs)
+    assert native.apsp_batch_candidate(native.apsp_batched_choice()).flags & native.FLAG_BATCH_QUEUE
+    big = torch.zeros(8193 * 8193, dtype=torch.int32, device=dev)
     with pytest.raises(native.ApspError) as e:
-        native.apsp_batched(flat, off_d, sz_d, hs)
+        native.apsp_batched(big, torch.zeros(1, dtype=torch.int64, device=dev),
+                            torch.full((1,), 8193, dtype=torch.int32, device=dev), [8193], batch_queue=True)
     assert e.value.status == native.APSP_E_UNSUPPORTED
+
+
+GLOBAL_CASES = [(1500, 0.01, {"batch_queue": True, "batch_global": True}),
+                (2500, 0.004, {"batch_queue": True, "batch_global": True, "block": 128, "tile": 64}),
+                (1200, 0.02, {"batch_queue": True, "batch_global": True, "block": 64}),
+                (2049, 0.003, {})]
+
+
+@pytest.mark.parametrize("n,p,kw", GLOBAL_CASES, ids=[f"n{n}_{i}" for i, (n, p, kw) in enumerate(GLOBAL_CASES)])
+def test_queue_large_single_graph(native, dev, n, p, kw):
+    """One graph above the lock-step limit through the queue schedule with
+    one queue for the device (its tasks run on every XCD; the automatic plan
+    takes this form for a batch of one), bit-exact against the oracle; a
+    second graph of other size in the same batch."""
+    rng = np.random.default_rng(n)
+    mats = []
+    for m in (n, 300):
+        W = np.where(rng.random((m, m)) < p * (n / m), rng.integers(1, 1000, (m, m)), INF).astype(np.int32)
+        np.fill_diagonal(W, 0)
+        mats.append(W)
+    flat, off_d, sz_d, hs, off = pack(mats, dev)
+    native.apsp_batched(flat, off_d, sz_d, hs, **kw)
+    assert native.apsp_batched_status() == 0
+    got = unpack(flat, off, hs)
+    for W, g in zip(mats, got):
+        np.testing.assert_array_equal(g, oracle.fw_i32(W, threads=16), err_msg=f"n={W.shape[0]} {kw}")
 
 
 def test_batched_workspace_contract(native, dev):
