@@ -35,7 +35,7 @@ DRIVER = textwrap.dedent(r"""
         EXPECT(apsp_validate(NULL, APSP_I32, 4, fake, 4, NULL, NULL) == APSP_E_ARG);
         EXPECT(apsp_validate(NULL, APSP_I32, 4, fake, 4, NULL, &v) == APSP_E_ARG);
         EXPECT(apsp_predecessors(NULL, APSP_I32, 4, fake, 4, fake, 4, (int32_t *)fake, 4, NULL) == APSP_E_ARG);
-        int32_t sizes[2] = {3, 2000};
+        int32_t sizes[2] = {3, 9000};
         EXPECT(apsp_batched(NULL, APSP_I32, 2, fake, fake, fake, sizes, NULL, NULL) == APSP_E_UNSUPPORTED);
         EXPECT(apsp_batched(NULL, APSP_I32, -1, fake, fake, fake, sizes, NULL, NULL) == APSP_E_ARG);
         EXPECT(apsp_plan(NULL, APSP_I32, 100, 0.1, 1, 1, NULL, NULL) == APSP_E_ARG);
