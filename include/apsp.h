@@ -97,6 +97,14 @@ typedef int32_t apsp_dtype_t;
 #define APSP_FLAG_BATCH_LOCKSTEP   256 /* apsp_batched: the lock-step schedule (see apsp_batched) */
 #define APSP_FLAG_BATCH_GLOBAL     512 /* apsp_batched with APSP_FLAG_BATCH_QUEUE: one ticket queue for the
                                           whole device instead of one per XCD (see apsp_batched) */
+#define APSP_FLAG_DETERMINISTIC    1024 /* apsp_fw / apsp_rkleene / apsp_solve: results identical bit for bit
+                                          from run to run (fp32; int32 results are unique anyway).  Every
+                                          product whose output block is also one of its operands (R-Kleene's
+                                          B <- A*B, C <- CA*, B <- BD*, C <- D*C; blocked FW's panels) reads
+                                          a copy of that operand taken first, so no tile reads entries that
+                                          other workgroups are lowering.  Needs a workspace of
+                                          apsp_workspace_size(APSP_OP_DETERMINISTIC, n) (APSP_E_NOMEM
+                                          otherwise); apsp_square rejects it (APSP_E_UNSUPPORTED). */
 #define APSP_FLAG_SKIP_INF         64 /* minplus_gemm / apsp_fw / apsp_rkleene / apsp_square / apsp_solve:
                                          a product skips every reduction slice (16 or 32 steps of one
                                          tile) whose A block or B block is all INF -- exact, since
@@ -147,13 +155,17 @@ const char *apsp_version(void);
  *                         that shape;
  *   APSP_OP_PREDECESSORS  n_or_total = n: the sparse form for every graph the
  *                         automatic choice takes sparse (up to n^2/4 edges);
- *                         0 for n > 65535 (dense only).
+ *                         0 for n > 65535 (dense only);
+ *   APSP_OP_DETERMINISTIC n_or_total = n: the copies APSP_FLAG_DETERMINISTIC
+ *                         takes for apsp_fw / apsp_rkleene / apsp_solve
+ *                         (about n^2 / 2 elements for R-Kleene).
  * Returns 0 (and sets the last error) for an invalid context, dtype, op or
  * negative size.
  */
 #define APSP_OP_SOLVE        0
 #define APSP_OP_BATCHED      1
 #define APSP_OP_PREDECESSORS 2
+#define APSP_OP_DETERMINISTIC 3
 size_t apsp_workspace_size(apsp_ctx_t *ctx, int32_t op, apsp_dtype_t dtype, int64_t n_or_total, int32_t count);
 
 /*

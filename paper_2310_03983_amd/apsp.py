@@ -29,6 +29,7 @@ FLAG_SKIP_INF = 64
 FLAG_BATCH_QUEUE = 128
 FLAG_BATCH_LOCKSTEP = 256
 FLAG_BATCH_GLOBAL = 512
+FLAG_DETERMINISTIC = 1024
 CAP16 = 0x39FF    # 14847: cap of the APSP_FLAG_PACKED16 products
 
 # every symbol include/apsp.h declares
@@ -48,7 +49,7 @@ EXPORTS = [
 ]
 # the trained cost model shipped with the package (plain-text model file)
 MODEL_PATH = os.path.join(_PKG, "data", "costmodel_mlp.txt")
-OP = {"solve": 0, "batched": 1, "predecessors": 2}
+OP = {"solve": 0, "batched": 1, "predecessors": 2, "deterministic": 3}
 FOLD = {"int32": 0, "float32": 1, "packed16": 2}
 PRED = {"auto": 0, "dense": 1, "sparse": 2}
 
@@ -81,7 +82,7 @@ class KernelStats(ctypes.Structure):
 def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, splitk=True,
               batch_graph=True, batch_per_graph=False, lookahead=True, batch_persistent=False,
               packed16=False, skip_inf=False, batch_queue=False, batch_lockstep=False,
-              batch_global=False) -> Opts:
+              batch_global=False, deterministic=False) -> Opts:
     o = Opts()
     o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
     o.block = int(block)
@@ -92,7 +93,8 @@ def make_opts(algo="auto", block=0, tile="auto", closure="auto", cutover=0, spli
         (FLAG_BATCH_PER_GRAPH if batch_per_graph else 0) | (0 if lookahead else FLAG_NO_LOOKAHEAD) | \
         (FLAG_BATCH_PERSISTENT if batch_persistent else 0) | (FLAG_PACKED16 if packed16 else 0) | \
         (FLAG_SKIP_INF if skip_inf else 0) | (FLAG_BATCH_QUEUE if batch_queue else 0) | \
-        (FLAG_BATCH_LOCKSTEP if batch_lockstep else 0) | (FLAG_BATCH_GLOBAL if batch_global else 0)
+        (FLAG_BATCH_LOCKSTEP if batch_lockstep else 0) | (FLAG_BATCH_GLOBAL if batch_global else 0) | \
+        (FLAG_DETERMINISTIC if deterministic else 0)
     return o
 
 
@@ -274,6 +276,8 @@ def _square_call(name, D, opts, stream, kw):
     if D.shape[1] != n:
         raise ValueError("D must be square")
     o = _opts(opts, kw)
+    if o.flags & FLAG_DETERMINISTIC and name in ("apsp_fw", "apsp_rkleene", "apsp_solve") and D.is_cuda:
+        _ensure_workspace("deterministic", dt, n, 0, D.device.index)
     _check(getattr(lib(), name)(context(D.device.index), dt, n, p, ld, ctypes.byref(o), _stream(D, stream)))
     return D
 

@@ -230,6 +230,8 @@ struct Plan {
     bool lookahead; // FW: overlap the next pivot and panels with the remainder
     bool p16;       // int32: min-plus products in capped 16-bit arithmetic
     bool skip;      // products skip reduction slices with an all-INF operand
+    bool det;       // aliased product operands are read from a copy (tmp)
+    void* tmp = nullptr;   // workspace for those copies (det)
 };
 
 Plan resolve(const apsp_opts_t* o)
@@ -242,6 +244,7 @@ Plan resolve(const apsp_opts_t* o)
     p.splitk = !(o->flags & APSP_FLAG_NO_SPLITK);
     p.lookahead = !(o->flags & APSP_FLAG_NO_LOOKAHEAD);
     p.p16 = (o->flags & APSP_FLAG_PACKED16) != 0;
+    p.det = (o->flags & APSP_FLAG_DETERMINISTIC) != 0;
     p.skip = (o->flags & APSP_FLAG_SKIP_INF) != 0;
     return p;
 }
@@ -334,6 +337,18 @@ apsp_status_t closure(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int
 // ---------------------------------------------------------------------------
 // phases 1 and 2 of round (k0, bk): close the pivot tile, then the row panel
 // R_KJ <- X* (min,+) R_KJ and the column panel C_IK <- C_IK (min,+) X*
+// rows x cols block at (r, c) of D (stride ld) into dst (stride dld), on st
+apsp_status_t copy_block(apsp_dtype_t dt, void* dst, int64_t dld, const void* D, int64_t ld, int64_t r, int64_t c,
+                         int64_t rows, int64_t cols, hipStream_t st)
+{
+    if (rows <= 0 || cols <= 0) return APSP_OK;
+    const size_t e = esize(dt);
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)dld * e, elem(const_cast<void*>(D), dt, r, c, ld), (size_t)ld * e,
+                             (size_t)cols * e, (size_t)rows, hipMemcpyDeviceToDevice, st),
+            "operand copy");
+    return APSP_OK;
+}
+
 apsp_status_t fw_panels(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
                         int64_t k0, int64_t bk, const Plan& pl, hipStream_t st)
 {
@@ -348,6 +363,21 @@ apsp_status_t fw_panels(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
     g2.p[1] = make_problem(dt, D, ld, off, off + k0, off + k0, off + k0, off, off + k0, n, bk, bk);
     g2.p[1].skip_m0 = (int32_t)(k0 / s2.mt);
     g2.p[1].skip_mc = (int32_t)((bk + s2.mt - 1) / s2.mt);
+    if (pl.det) {
+        // the row panel (bk x n) and the column panel (n x bk) are read from
+        // copies: a 64-tile of the band would otherwise read the band's other
+        // tile rows (columns) while their workgroups lower them
+        char* rowc = static_cast<char*>(pl.tmp);
+        char* colc = rowc + (size_t)bk * n * esize(dt);
+        apsp_status_t rc;
+        if ((rc = copy_block(dt, rowc, n, D, ld, off + k0, off, bk, n, st)) ||
+            (rc = copy_block(dt, colc, bk, D, ld, off, off + k0, n, bk, st)))
+            return rc;
+        g2.p[0].B = rowc;
+        g2.p[0].ldb = n;
+        g2.p[1].A = colc;
+        g2.p[1].lda = bk;
+    }
     return run_group(ctx, dt, g2, pl, t_p2, st);
 }
 
@@ -476,6 +506,37 @@ apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
 // ---------------------------------------------------------------------------
 // R-Kleene on the window [off, off+n)^2 (Sec. 3.3, Eq. 4)
 // ---------------------------------------------------------------------------
+// Deterministic mode: the B block (rows a.., columns d.., n1 x n2) and the C
+// block (rows d.., columns a.., n2 x n1) are copied to the workspace and the
+// products that update them read the copy in place of the block itself
+// (as operand B when b_is_B, else as operand A; likewise for C).
+apsp_status_t aliased_from_copies(apsp_dtype_t dt, void* D, int64_t ld, int64_t a, int64_t d, int64_t n1,
+                                  int64_t n2, const Plan& pl, apsp::GemmProblem& pb, bool b_is_B,
+                                  apsp::GemmProblem& pc, bool c_is_B, hipStream_t st)
+{
+    char* bcopy = static_cast<char*>(pl.tmp);
+    char* ccopy = bcopy + (size_t)n1 * n2 * esize(dt);
+    apsp_status_t rc;
+    if ((rc = copy_block(dt, bcopy, n2, D, ld, a, d, n1, n2, st)) ||
+        (rc = copy_block(dt, ccopy, n1, D, ld, d, a, n2, n1, st)))
+        return rc;
+    if (b_is_B) {
+        pb.B = bcopy;
+        pb.ldb = n2;
+    } else {
+        pb.A = bcopy;
+        pb.lda = n2;
+    }
+    if (c_is_B) {
+        pc.B = ccopy;
+        pc.ldb = n1;
+    } else {
+        pc.A = ccopy;
+        pc.lda = n1;
+    }
+    return APSP_OK;
+}
+
 apsp_status_t rk_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, int64_t off, int64_t n,
                         const Plan& pl, hipStream_t st)
 {
@@ -492,19 +553,23 @@ apsp_status_t rk_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
     // A <- A*
     if ((rc = rk_window(ctx, dt, D, ld, a, n1, pl, st))) return rc;
     // B <- min(B, A (min,+) B);  C <- min(C, C (min,+) A)
-    rc = run_two(ctx, dt,
-                 make_problem(dt, D, ld, a, a, a, d, a, d, n1, n2, n1),
-                 make_problem(dt, D, ld, d, a, a, a, d, a, n2, n1, n1), pl, st);
-    if (rc) return rc;
+    {
+        apsp::GemmProblem pb = make_problem(dt, D, ld, a, a, a, d, a, d, n1, n2, n1);
+        apsp::GemmProblem pc = make_problem(dt, D, ld, d, a, a, a, d, a, n2, n1, n1);
+        if (pl.det && (rc = aliased_from_copies(dt, D, ld, a, d, n1, n2, pl, pb, true, pc, false, st))) return rc;
+        if ((rc = run_two(ctx, dt, pb, pc, pl, st))) return rc;
+    }
     // D <- min(D, C (min,+) B)
     if ((rc = run_one(ctx, dt, make_problem(dt, D, ld, d, a, a, d, d, d, n2, n2, n1), pl, st))) return rc;
     // D <- D*
     if ((rc = rk_window(ctx, dt, D, ld, d, n2, pl, st))) return rc;
     // B <- min(B, B (min,+) D);  C <- min(C, D (min,+) C)
-    rc = run_two(ctx, dt,
-                 make_problem(dt, D, ld, a, d, d, d, a, d, n1, n2, n2),
-                 make_problem(dt, D, ld, d, d, d, a, d, a, n2, n1, n2), pl, st);
-    if (rc) return rc;
+    {
+        apsp::GemmProblem pb = make_problem(dt, D, ld, a, d, d, d, a, d, n1, n2, n2);
+        apsp::GemmProblem pc = make_problem(dt, D, ld, d, d, d, a, d, a, n2, n1, n2);
+        if (pl.det && (rc = aliased_from_copies(dt, D, ld, a, d, n1, n2, pl, pb, false, pc, true, st))) return rc;
+        if ((rc = run_two(ctx, dt, pb, pc, pl, st))) return rc;
+    }
     // A <- min(A, B (min,+) C)
     return run_one(ctx, dt, make_problem(dt, D, ld, a, d, d, a, a, a, n1, n1, n2), pl, st);
 }
@@ -722,6 +787,28 @@ size_t pred_ws_bytes(int64_t n)
 // Planner feature pass of apsp_solve / apsp_features: a union-find parent
 // per vertex (counters in the context scratch).
 size_t solve_ws_bytes(int64_t n) { return kWsAlign + align_up((size_t)n * sizeof(int32_t)); }
+
+// APSP_FLAG_DETERMINISTIC: R-Kleene's top-level B and C copies (2 n1 n2 <=
+// 2 floor(n^2 / 4) elements for any split n1 + n2 = n) or blocked FW's panel
+// copies (2 x 128 x n), whichever is larger; the recursion reuses the same
+// memory in stream order.
+size_t det_ws_bytes(int64_t n)
+{
+    if (n <= 1) return 0;
+    return align_up((size_t)std::max<int64_t>(2 * ((n * n) / 4), 2 * 128 * n) * sizeof(int32_t));
+}
+
+// Points the plan at the workspace for the deterministic copies, or fails.
+apsp_status_t det_workspace(apsp_ctx_t* ctx, int64_t n, Plan& pl)
+{
+    if (!pl.det) return APSP_OK;
+    const size_t need = det_ws_bytes(n);
+    if (!ctx->ws || ctx->ws_bytes < need)
+        return fail(APSP_E_NOMEM, "APSP_FLAG_DETERMINISTIC needs a workspace of %zu bytes (apsp_workspace_size)", need);
+    pl.tmp = ctx->ws;
+    ctx->ws_owner = WS_NONE;
+    return APSP_OK;
+}
 
 // Batched plan: [pointer record][ticket, error word][queue order]
 // [lock-step items][queue tasks][queue counters], each part 256-aligned.
@@ -1009,6 +1096,7 @@ size_t apsp_workspace_size(apsp_ctx_t* ctx, int32_t op, apsp_dtype_t dt, int64_t
     case APSP_OP_PREDECESSORS:
         if (n_or_total <= 1 || n_or_total > kPredSparseMaxN) return 0;
         return pred_ws_bytes(n_or_total);
+    case APSP_OP_DETERMINISTIC: return det_ws_bytes(n_or_total);
     default:
         fail(APSP_E_ARG, "op = %d", op);
         return 0;
@@ -1087,6 +1175,7 @@ apsp_status_t apsp_fw(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, int6
     if ((rc = check_opts(o)) || (rc = check_packed16(dt, o)) || (rc = check_ctx(ctx))) return rc;
     if (n <= 1) return APSP_OK;
     Plan pl = resolve(o);
+    if ((rc = det_workspace(ctx, n, pl))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((rc = fw_window(ctx, dt, D, ldd, 0, n, pl, st)) || !pl.p16) return rc;
     return finish_packed16(ctx, n, D, ldd, st, [&] {
@@ -1104,6 +1193,7 @@ apsp_status_t apsp_rkleene(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D,
     if ((rc = check_opts(o)) || (rc = check_packed16(dt, o)) || (rc = check_ctx(ctx))) return rc;
     if (n <= 1) return APSP_OK;
     Plan pl = resolve(o);
+    if ((rc = det_workspace(ctx, n, pl))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((rc = rk_window(ctx, dt, D, ldd, 0, n, pl, st)) || !pl.p16) return rc;
     return finish_packed16(ctx, n, D, ldd, st, [&] {
@@ -1119,6 +1209,8 @@ apsp_status_t apsp_square(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D, 
     if ((rc = check_dtype(dt)) || (rc = check_square(n, D, ldd))) return rc;
     const apsp_opts_t* o = opts_or_default(opts);
     if ((rc = check_opts(o)) || (rc = check_packed16(dt, o)) || (rc = check_ctx(ctx))) return rc;
+    if (o->flags & APSP_FLAG_DETERMINISTIC)
+        return fail(APSP_E_UNSUPPORTED, "apsp_square has no deterministic mode (use apsp_fw or apsp_rkleene)");
     if (n <= 1) return APSP_OK;
     Plan pl = resolve(o);
     hipStream_t st = static_cast<hipStream_t>(stream);

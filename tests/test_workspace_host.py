@@ -74,6 +74,16 @@ assert L.apsp_path(c, 10, fake, 10, 1, fake, fake, fake, 0, fake, None) == a.APS
 assert L.apsp_path(c, 10, fake, 10, 1, None, fake, fake, 10, fake, None) == a.APSP_E_ARG
 assert L.apsp_path(c, 10, fake, 9, 1, fake, fake, fake, 10, fake, None) == a.APSP_E_ARG
 assert L.apsp_path(c, 10, fake, 10, 0, None, None, None, 10, None, None) == 0
+# deterministic mode: copies of the aliased operands (about n^2 / 2 elements)
+assert ws(c, 3, 1, 1000, 0) == al(max(2 * (1000 * 1000 // 4), 256 * 1000) * 4)
+assert ws(c, 3, 0, 100, 0) == al(256 * 100 * 4)
+assert ws(c, 3, 1, 1, 0) == 0
+od = a.make_opts(deterministic=True)
+assert L.apsp_set_workspace(c, None, 0) == 0
+for fn in (L.apsp_rkleene, L.apsp_fw, L.apsp_solve):
+    rc = fn(c, 1, 1000, fake, 1000, ctypes.byref(od), None)
+    assert rc == a.APSP_E_NOMEM and "DETERMINISTIC" in a.last_error(), (rc, a.last_error())
+assert L.apsp_square(c, 1, 1000, fake, 1000, ctypes.byref(od), None) == a.APSP_E_UNSUPPORTED
 # squaring pass count: nothing to report before the first apsp_square
 npass = ctypes.c_int32(7)
 assert L.apsp_square_passes(c, None, ctypes.byref(npass)) == a.APSP_E_STATE
