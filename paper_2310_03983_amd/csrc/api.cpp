@@ -589,7 +589,7 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld)
 
 // Squaring runs as one launch up to this size (its passes are latency-bound
 // there); larger graphs take one launch and one flag read-back per pass.
-constexpr int64_t kCoopSquareMaxN = 2048;
+constexpr int64_t kFlowSquareMaxN = 2048;
 constexpr int kSquarePassesWord = 50;   // in the synchronisation block below
 // tickets, pass counters, flags and pass count of the one-launch squaring
 // (scratch bytes 256 .. 511)
@@ -599,7 +599,7 @@ apsp_status_t square_common(apsp_ctx_t* ctx, apsp_dtype_t dt, int64_t n, void* D
                             const Plan& pl, hipStream_t st)
 {
     if (n <= 1) return APSP_OK;
-    if (!pl.p16 && !pl.skip && n <= kCoopSquareMaxN) {
+    if (!pl.p16 && !pl.skip && n <= kFlowSquareMaxN) {
         // small graph: every pass in one launch, no read-back
         if (fault_injected("launch")) return fail(APSP_E_HIP, "injected launch failure");
         ctx->square_passes = 0;

@@ -1,11 +1,11 @@
-"""GPU parity of whole-graph squaring (Sec. 3.2) in its one-launch forms
-(apsp_square for n <= 2048: every pass in one cooperative launch with a
-device-wide barrier and a device "changed" flag; n <= 512 with whole
-strips staged in LDS, larger n with sliced 32- or 64-tiles): int32 bit-exact against
-the oracle's Eq. 1 loop, fp32 within 1e-5 of the fp64 oracle, on graphs that
-need the most passes (a path through every vertex), disconnected graphs,
-strided views, ragged sizes, and back-to-back calls (the flags and the
-barrier counter are reset per launch)."""
+"""GPU parity of whole-graph squaring (Sec. 3.2) in its one-launch form
+(apsp_square for n <= 2048: every pass inside one launch, tasks of a pass
+waiting on the previous pass's counter, convergence detected on the
+device): int32 bit-exact against the oracle's Eq. 1 loop, fp32 within 1e-5
+of the fp64 oracle, on graphs that need the most passes (a path through
+every vertex), disconnected graphs, strided views, ragged sizes, and
+back-to-back calls (the counters are reset per launch); the reported pass
+count stays within ceil(log2(n - 1))."""
 import os
 
 import numpy as np
