@@ -19,12 +19,14 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace apsp {
 
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int32_t kSampleMinN = 1024;   // graphs from this size join a sample first
 
 // Parent reads go through the caches and may return an older parent: every
 // value a vertex ever had is an ancestor of it (parents only move up), so a
@@ -94,24 +96,51 @@ __global__ __launch_bounds__(kThreads) void k_features_init(int32_t* parent, int
 // accesses in flight per lane.  Each lane keeps a root of the row's tree; an
 // edge whose other end has that vertex as its parent is already inside the
 // tree and skips the join.
-template <class T>
-__device__ __forceinline__ void visit(int32_t* parent, int32_t& ri, int32_t r, int32_t c, T w, uint32_t& cnt)
+//
+// Passes: kAll counts every edge and joins every edge.  For larger graphs a
+// sample comes first: kSample counts every edge but joins only the first
+// kWaveSample edges each wave meets in a row (chosen by a wave vote); if
+// the sampled subgraph is already connected, so is the graph, and kRest
+// (which joins every edge, without counting) returns at once; otherwise
+// kRest completes the forest.  On a Bernoulli graph a few edges per vertex
+// connect it, so the common case joins a fraction of the edges.
+enum JoinPass { kAll = 0, kSample = 1, kRest = 2 };
+constexpr int kWaveSample = 8;
+
+template <class T, int PASS>
+__device__ __forceinline__ void visit(int32_t* parent, int32_t& ri, int32_t r, int32_t c, T w, uint32_t& cnt,
+                                      int& taken)
 {
-    if (c == r || !edge<T>(w)) return;
-    ++cnt;
-    if (load_parent(parent, c) != ri) join(parent, ri, c);
+    const bool e = c != r && edge<T>(w);
+    if constexpr (PASS != kRest) cnt += e;
+    if constexpr (PASS == kSample) {
+        const unsigned long long mask = __ballot(e);
+        if (e) {
+            const int lane = threadIdx.x & 63;
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));   // voting lanes below this one
+            if (taken + rank < kWaveSample && load_parent(parent, c) != ri) join(parent, ri, c);
+        }
+        taken += __popcll(mask);
+    } else {
+        if (e && load_parent(parent, c) != ri) join(parent, ri, c);
+    }
 }
 
-template <class T>
+template <class T, int PASS>
 __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ D, int32_t n, int64_t ld,
-                                                          int32_t* parent, unsigned long long* edges)
+                                                          int32_t* parent, unsigned long long* edges,
+                                                          const uint32_t* connected)
 {
     using V = dev::Pair2<dev::Pair2<T>>;   // four elements, one dwordx4 access
     constexpr int kStep = 4 * kThreads;
+    if constexpr (PASS == kRest) {
+        if (*connected) return;   // the sample already connected the graph
+    }
     uint32_t cnt = 0;
     for (int32_t r = blockIdx.x; r < n; r += gridDim.x) {
         const T* row = D + (int64_t)r * ld;
         int32_t ri = find_root(parent, r);
+        int taken = 0;   // sampled joins of this wave in this row
         int32_t c = threadIdx.x * 4;
         for (; c + 3 * kStep + 3 < n; c += 4 * kStep) {
             V v[4];
@@ -120,29 +149,48 @@ __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int32_t c0 = c + q * kStep;
-                visit<T>(parent, ri, r, c0, v[q].x.x, cnt);
-                visit<T>(parent, ri, r, c0 + 1, v[q].x.y, cnt);
-                visit<T>(parent, ri, r, c0 + 2, v[q].y.x, cnt);
-                visit<T>(parent, ri, r, c0 + 3, v[q].y.y, cnt);
+                visit<T, PASS>(parent, ri, r, c0, v[q].x.x, cnt, taken);
+                visit<T, PASS>(parent, ri, r, c0 + 1, v[q].x.y, cnt, taken);
+                visit<T, PASS>(parent, ri, r, c0 + 2, v[q].y.x, cnt, taken);
+                visit<T, PASS>(parent, ri, r, c0 + 3, v[q].y.y, cnt, taken);
             }
         }
         for (; c + 3 < n; c += kStep) {
             const V v = dev::ld_vec<V>(row + c);
-            visit<T>(parent, ri, r, c, v.x.x, cnt);
-            visit<T>(parent, ri, r, c + 1, v.x.y, cnt);
-            visit<T>(parent, ri, r, c + 2, v.y.x, cnt);
-            visit<T>(parent, ri, r, c + 3, v.y.y, cnt);
+            visit<T, PASS>(parent, ri, r, c, v.x.x, cnt, taken);
+            visit<T, PASS>(parent, ri, r, c + 1, v.x.y, cnt, taken);
+            visit<T, PASS>(parent, ri, r, c + 2, v.y.x, cnt, taken);
+            visit<T, PASS>(parent, ri, r, c + 3, v.y.y, cnt, taken);
         }
-        for (; c < n; ++c) visit<T>(parent, ri, r, c, row[c], cnt);
+        for (; c < n; ++c) visit<T, PASS>(parent, ri, r, c, row[c], cnt, taken);
     }
+    if constexpr (PASS != kRest) {
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        __shared__ uint32_t part[kThreads / 64];
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < kThreads / 64; ++w) tot += part[w];
+            if (tot) atomicAdd(edges, tot);
+        }
+    }
+}
+
+// One workgroup: *connected = 1 when the forest has one root.
+constexpr int kRootThreads = 1024;
+__global__ __launch_bounds__(kRootThreads) void k_one_root(const int32_t* parent, int32_t n, uint32_t* connected)
+{
+    uint32_t cnt = 0;
+    for (int32_t v = threadIdx.x; v < n; v += kRootThreads) cnt += parent[v] == v;
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-    __shared__ uint32_t part[kThreads / 64];
+    __shared__ uint32_t part[kRootThreads / 64];
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long tot = 0;
-        for (int w = 0; w < kThreads / 64; ++w) tot += part[w];
-        if (tot) atomicAdd(edges, tot);
+        uint32_t roots = 0;
+        for (int w = 0; w < kRootThreads / 64; ++w) roots += part[w];
+        *connected = roots == 1u ? 1u : 0u;
     }
 }
 
@@ -179,12 +227,27 @@ hipError_t launch_graph_features(DType dt, const void* D, int32_t n, int64_t ld,
     hipLaunchKernelGGL(k_features_init, dim3(gi), dim3(kThreads), 0, st, parent, n > 1 ? n : 0, edges, roots);
     if (n > 1) {
         const int gr = (int)std::min<int64_t>(n, 4096);
-        if (dt == F32)
-            hipLaunchKernelGGL(k_graph_edges<float>, dim3(gr), dim3(kThreads), 0, st, (const float*)D, n, ld, parent,
-                               edges);
-        else
-            hipLaunchKernelGGL(k_graph_edges<uint32_t>, dim3(gr), dim3(kThreads), 0, st, (const uint32_t*)D, n, ld,
-                               parent, edges);
+        auto pass = [&](auto tag, auto pass_c) {
+            using T = decltype(tag);
+            constexpr int PASS = decltype(pass_c)::value;
+            hipLaunchKernelGGL((k_graph_edges<T, PASS>), dim3(gr), dim3(kThreads), 0, st, static_cast<const T*>(D), n,
+                               ld, parent, edges, roots);
+        };
+        using All = std::integral_constant<int, kAll>;
+        using Sample = std::integral_constant<int, kSample>;
+        using Rest = std::integral_constant<int, kRest>;
+        if (n < kSampleMinN) {
+            if (dt == F32) pass(float{}, All{});
+            else pass(uint32_t{}, All{});
+        } else {
+            // sampled joins, the one-root test (roots is its flag word), then
+            // the remaining joins unless the sample connected the graph
+            if (dt == F32) pass(float{}, Sample{});
+            else pass(uint32_t{}, Sample{});
+            hipLaunchKernelGGL(k_one_root, dim3(1), dim3(kRootThreads), 0, st, parent, n, roots);
+            if (dt == F32) pass(float{}, Rest{});
+            else pass(uint32_t{}, Rest{});
+        }
     }
     hipLaunchKernelGGL(k_features_finish, dim3(1), dim3(kFinishThreads), 0, st, parent, n > 1 ? n : 0, 1, edges, x);
     return hipGetLastError();
