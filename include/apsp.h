@@ -431,7 +431,8 @@ apsp_status_t apsp_batched(apsp_ctx_t *ctx, apsp_dtype_t dtype, int32_t count,
 /*
  * Diagnostic of the APSP_FLAG_BATCH_QUEUE schedule: *h_flags receives the
  * error word of the last batched plan (bit 0: a dependency wait overran its
- * bounded poll count since the last call, so that launch's results are not
+ * bounded poll count; bit 1: a queue handed out fewer tickets than it holds,
+ * i.e. some tasks did not run -- either means that launch's results are not
  * guaranteed) and the word is cleared.  Synchronises `stream`.  0 when no
  * batched plan is resident.
  */

@@ -378,6 +378,17 @@ void k_bqueue(const BatchPtrs* __restrict__ bp, const BatchTask* __restrict__ ta
     }
 }
 
+// After the queue kernel: every queue must have handed out all its tickets.
+// The grid holds qlen_max workgroups per XCD and workgroups are dispatched
+// to the XCDs in turn, so each queue meets at least its length in
+// workgroups; were a dispatch ever to leave one short, its last tasks would
+// be skipped silently, so the shortfall is reported in bit 1 of *err.
+__global__ void k_bqueue_claimed(const uint32_t* tickets, const int32_t* qoff, int nxcd, uint32_t* err)
+{
+    const int x = threadIdx.x;
+    if (x < nxcd && tickets[x * kTicketStride] < (uint32_t)(qoff[x + 1] - qoff[x])) atomicOr(err, 2u);
+}
+
 // Edges of every graph of a batch (finite off-diagonal entries), summed into
 // *total: one workgroup per graph (the batch planner's density input).
 template <class T>
@@ -493,6 +504,7 @@ hipError_t launch_batch_queue(DType dt, const BatchPtrs* bp, const BatchTask* ta
     else
         hipLaunchKernelGGL(k_bqueue<dev::SemF32>, dim3(grid), dim3(dev::kCloseWideThreads), 0, st, bp, tasks, qoff,
                            nxcd, tickets, counters, err, global ? 1 : 0);
+    hipLaunchKernelGGL(k_bqueue_claimed, dim3(1), dim3(64), 0, st, tickets, qoff, nxcd, err);
     return hipGetLastError();
 }
 
