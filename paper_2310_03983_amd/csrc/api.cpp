@@ -435,8 +435,16 @@ apsp_status_t fw_window(apsp_ctx_t* ctx, apsp_dtype_t dt, void* D, int64_t ld, i
                         const Plan& pl, hipStream_t st)
 {
     const int64_t b = pl.block;
-    // the excluded bands must be whole tiles: 64-wide rounds use 64-tiles
-    const int t_p3 = (b < 128) ? (int)apsp::TILE_64 : pick_tile(pl, n, n);
+    // the excluded bands must be whole tiles: 64-wide rounds use 64-tiles.
+    // The remainder's reduction is only one round wide, so a launch of
+    // 128-tiles ends in a long partial wave that keeps the second stream's
+    // panel products waiting for CUs; 64-tiles free slots sooner.  Measured
+    // (int32, p = 0.02): n = 3072 3.25 -> 2.38 ms, 4096 3.76 -> 3.40, 6144
+    // 10.1 -> 9.8, 8192 +2%; with capped 16-bit products 64-tiles also win
+    // at 8192 (18.9 -> 16.6 ms).
+    const int64_t rem64_max = pl.p16 ? 8192 : 6144;
+    const int t_p3 = (b < 128 || (pl.tile == APSP_TILE_AUTO && n <= rem64_max)) ? (int)apsp::TILE_64
+                                                                                 : pick_tile(pl, n, n);
     const apsp::TileShape s3 = apsp::tile_shape(t_p3), s64 = apsp::tile_shape(apsp::TILE_64);
     const int64_t rounds = (n + b - 1) / b;
     const bool ahead = pl.lookahead && rounds >= 3 && ctx->side && ctx->ev_a && ctx->ev_p;
