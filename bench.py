@@ -23,7 +23,8 @@ Reported alongside the headline:
                   of the fold's own instructions;
   measured_ceiling -- the same against the fold's issue rate measured by a
                   spin kernel on the device;
-  panel_phase  -- the FW panel products (64 x 64 tiles, K = 128):
+  fw_window_products -- the 64 x 64 products of the R-Kleene cutover
+                  windows (panels, band and remainder updates, K = 128):
                   compulsory HBM bytes / event-timed duration, GB/s against
                   the 8 TB/s HBM peak (recorded in one more solve);
   cpu_baseline -- the CPU oracle as it stands on the host's cores: the Eq. 1
@@ -526,10 +527,11 @@ def main():
         # the whole solve's rate against the published peak, 2 ops per term
         "valu_frac_whole_solve": 2.0 * value / PUBLISHED_PEAK_OPS,
         "roofline": roofline(k128, packed, fold_rate),
-        "panel_phase": {
+        "fw_window_products": {
             "kernel": "k_minplus<64x64 tile>" + (" (capped 16-bit)" if pkw["packed16"] else " (int32)"),
-            "what": "FW panel products of the R-Kleene cutover windows (row and column panels, K = 128), in a "
-                    "solve without look-ahead so that each launch runs alone",
+            "what": "the 64x64 products of the R-Kleene cutover windows (row and column panels, band updates and, "
+                    "up to n = 6144 (8192 capped), the remainder updates; K = 128), in a solve without look-ahead "
+                    "so that each launch runs alone",
             "launches_per_solve": k64["launches"],
             "ms_per_solve": k64["ms"],
             "bytes_per_launch": k64["bytes"] / max(k64["launches"], 1),
