@@ -1,9 +1,15 @@
-// Many independent graphs of uneven sizes closed in one persistent launch.
+// Many independent graphs of uneven sizes (a ragged batch) closed by blocked
+// Floyd-Warshall (Sec. 2, Eq. 1) in one of three schedules:
+//   the dependency-driven queue (k_bqueue, below): every pivot closure,
+//     panel tile and remainder tile of every graph is a task of its own;
+//   lock-step rounds (k_bclose, k_btile, k_bpivot, k_bsub): all graphs
+//     advance one 128-wide round per group of launches;
+//   one persistent kernel (k_batched, this first part).
 //
-// Every workgroup repeatedly takes the next graph from a queue (one atomic
-// ticket counter; the queue is ordered largest-first on the host, so the long
-// graphs start first and the small ones fill the tail) and solves that graph
-// on its own:
+// Persistent kernel: every workgroup repeatedly takes the next graph from a
+// queue (one atomic ticket counter; the queue is ordered largest-first on the
+// host, so the long graphs start first and the small ones fill the tail) and
+// solves that graph on its own:
 //   n <= 128: the whole matrix is closed in LDS by the block closure;
 //   n  > 128: blocked Floyd-Warshall (Sec. 2, Eq. 1) with 128-wide rounds --
 //            pivot closure, row/column panel tiles, remainder tiles -- all by

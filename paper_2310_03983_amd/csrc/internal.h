@@ -178,9 +178,10 @@ hipError_t launch_predecessors(DType dt, const void* D, int64_t ldd, const void*
 
 // ---- planner features (features.hip)
 // Edge count and weak connectivity of an n x n cost matrix: *edges (uint64)
-// and *roots (uint32, components) are zeroed first, parent (n int32) is a
-// union-find forest in the workspace; x[0..3] receives the cost model's
-// inputs (log2 n, log10 density, log2 batch = 0, connected).
+// and *roots (uint32: the sampled pass's one-root flag) are zeroed first,
+// parent (n int32) is a union-find forest in the workspace; x[0..3]
+// receives the cost model's inputs (log2 n, log10 density, log2 batch = 0,
+// connected).
 hipError_t launch_graph_features(DType dt, const void* D, int32_t n, int64_t ld, int32_t* parent,
                                  unsigned long long* edges, uint32_t* roots, float* x, hipStream_t st);
 
