@@ -98,32 +98,62 @@ __global__ __launch_bounds__(kThreads) void k_features_init(int32_t* parent, int
 // tree and skips the join.
 //
 // Passes: kAll counts every edge and joins every edge.  For larger graphs a
-// sample comes first: kSample counts every edge but joins only the first
-// kWaveSample edges each wave meets in a row (chosen by a wave vote); if
-// the sampled subgraph is already connected, so is the graph, and kRest
-// (which joins every edge, without counting) returns at once; otherwise
-// kRest completes the forest.  On a Bernoulli graph a few edges per vertex
-// connect it, so the common case joins a fraction of the edges.
+// sample comes first: kSample counts every edge and records at most
+// kWaveSample of them per wave and row (the lowest marked column of the
+// first lanes, in lane order, that have one) in LDS; the workgroup joins the
+// recorded edges after its last row, one lane per row and wave, so that the
+// latency of the joins does not hold up the stream of loads.  If the
+// sampled subgraph is already connected, so is the graph, and kRest (which
+// joins every edge, without counting) returns at once; otherwise kRest
+// completes the forest.  On a Bernoulli graph a few edges per vertex
+// connect it, so the common case joins a small fraction of the edges.
+//
+// The count is branch-free: a lane folds the finite tests of its sixteen
+// elements into one mask and adds its population count; only lanes with a
+// marked element enter the join or record code.
 enum JoinPass { kAll = 0, kSample = 1, kRest = 2 };
-constexpr int kWaveSample = 8;
+constexpr int kWaveSample = 4;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxSampleRows = 64;   // rows of one workgroup in the sampled pass (the launch ensures it)
 
-template <class T, int PASS>
-__device__ __forceinline__ void visit(int32_t* parent, int32_t& ri, int32_t r, int32_t c, T w, uint32_t& cnt,
-                                      int& taken)
+// Joins every edge marked in mask (bit b: column col0 + (b / 4) * stride +
+// b % 4) to the row's tree.
+__device__ __forceinline__ void join_marked(int32_t* parent, int32_t& ri, uint32_t mask, int32_t col0, int32_t stride)
 {
-    const bool e = c != r && edge<T>(w);
-    if constexpr (PASS != kRest) cnt += e;
-    if constexpr (PASS == kSample) {
-        const unsigned long long mask = __ballot(e);
-        if (e) {
-            const int lane = threadIdx.x & 63;
-            const int rank = __popcll(mask & ((1ull << lane) - 1ull));   // voting lanes below this one
-            if (taken + rank < kWaveSample && load_parent(parent, c) != ri) join(parent, ri, c);
-        }
-        taken += __popcll(mask);
-    } else {
-        if (e && load_parent(parent, c) != ri) join(parent, ri, c);
+    while (mask) {
+        const int b = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        const int32_t c = col0 + (b >> 2) * stride + (b & 3);
+        if (load_parent(parent, c) != ri) join(parent, ri, c);
     }
+}
+
+// Records the lowest marked column of this lane in the wave's next free
+// slot of the row, for the first kWaveSample marked lanes; taken counts the
+// wave's marked lanes so far in the row.  (Where lanes have diverged, two
+// may pick one slot or leave one empty: a slot only ever holds -1 or an
+// edge of the row.)
+__device__ __forceinline__ void sample_marked(int32_t* slots, uint32_t mask, int32_t col0, int32_t stride, int& taken)
+{
+    if (taken >= kWaveSample) return;
+    const unsigned long long voters = __ballot(mask != 0u);
+    if (mask) {
+        const int lane = threadIdx.x & 63;
+        const int slot = taken + __popcll(voters & ((1ull << lane) - 1ull));
+        if (slot < kWaveSample) {
+            const int b = __builtin_ctz(mask);
+            slots[slot] = col0 + (b >> 2) * stride + (b & 3);
+        }
+    }
+    taken += __popcll(voters);
+}
+
+// Bit e of the result: element e of the four (columns c .. c + 3) is an edge.
+template <class T>
+__device__ __forceinline__ uint32_t edge_bits(const dev::Pair2<dev::Pair2<T>>& v, int32_t c, int32_t r)
+{
+    return (uint32_t)(edge<T>(v.x.x) && c != r) | ((uint32_t)(edge<T>(v.x.y) && c + 1 != r) << 1) |
+           ((uint32_t)(edge<T>(v.y.x) && c + 2 != r) << 2) | ((uint32_t)(edge<T>(v.y.y) && c + 3 != r) << 3);
 }
 
 template <class T, int PASS>
@@ -136,33 +166,52 @@ __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ 
     if constexpr (PASS == kRest) {
         if (*connected) return;   // the sample already connected the graph
     }
+    constexpr int kSlots = PASS == kSample ? kMaxSampleRows * kWaves * kWaveSample : 1;
+    __shared__ int32_t s_slots[kSlots];   // recorded edges, by (local row, wave, slot); -1 = none
+    if constexpr (PASS == kSample) {
+        for (int i = threadIdx.x; i < kSlots; i += kThreads) s_slots[i] = -1;
+        __syncthreads();
+    }
     uint32_t cnt = 0;
-    for (int32_t r = blockIdx.x; r < n; r += gridDim.x) {
+    int rows = 0;   // rows this workgroup has taken
+    for (int32_t r = blockIdx.x; r < n; r += gridDim.x, ++rows) {
         const T* row = D + (int64_t)r * ld;
-        int32_t ri = find_root(parent, r);
-        int taken = 0;   // sampled joins of this wave in this row
+        int32_t ri = r;
+        if constexpr (PASS != kSample) ri = find_root(parent, r);
+        // kSample: this wave's slots of the row (nothing is recorded past kMaxSampleRows)
+        int32_t* slots = s_slots + (rows * kWaves + (threadIdx.x >> 6)) * kWaveSample;
+        int taken = PASS == kSample && rows < kMaxSampleRows ? 0 : kWaveSample;
+        auto visit = [&](uint32_t mask, int32_t col0, int32_t stride) {
+            if constexpr (PASS != kRest) cnt += __popc(mask);
+            if constexpr (PASS == kSample) sample_marked(slots, mask, col0, stride, taken);
+            else join_marked(parent, ri, mask, col0, stride);
+        };
         int32_t c = threadIdx.x * 4;
         for (; c + 3 * kStep + 3 < n; c += 4 * kStep) {
             V v[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) v[q] = dev::ld_vec<V>(row + c + q * kStep);
+            uint32_t mask = 0;   // bit 4q + e: element e of access q
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t c0 = c + q * kStep;
-                visit<T, PASS>(parent, ri, r, c0, v[q].x.x, cnt, taken);
-                visit<T, PASS>(parent, ri, r, c0 + 1, v[q].x.y, cnt, taken);
-                visit<T, PASS>(parent, ri, r, c0 + 2, v[q].y.x, cnt, taken);
-                visit<T, PASS>(parent, ri, r, c0 + 3, v[q].y.y, cnt, taken);
+            for (int q = 0; q < 4; ++q) mask |= edge_bits<T>(v[q], c + q * kStep, r) << (4 * q);
+            visit(mask, c, kStep);
+        }
+        for (; c + 3 < n; c += kStep) visit(edge_bits<T>(dev::ld_vec<V>(row + c), c, r), c, kStep);
+        for (; c < n; ++c) visit((edge<T>(row[c]) && c != r) ? 1u : 0u, c, 0);
+    }
+    if constexpr (PASS == kSample) {
+        // the recorded edges: one lane per (row, wave), its slots in order
+        __syncthreads();
+        const int pairs = (rows < kMaxSampleRows ? rows : kMaxSampleRows) * kWaves;
+        for (int i = threadIdx.x; i < pairs; i += kThreads) {
+            const int32_t r = blockIdx.x + (i / kWaves) * gridDim.x;
+            int32_t ri = find_root(parent, r);
+            for (int k = 0; k < kWaveSample; ++k) {
+                const int32_t c = s_slots[i * kWaveSample + k];
+                if (c < 0) break;
+                if (load_parent(parent, c) != ri) join(parent, ri, c);
             }
         }
-        for (; c + 3 < n; c += kStep) {
-            const V v = dev::ld_vec<V>(row + c);
-            visit<T, PASS>(parent, ri, r, c, v.x.x, cnt, taken);
-            visit<T, PASS>(parent, ri, r, c + 1, v.x.y, cnt, taken);
-            visit<T, PASS>(parent, ri, r, c + 2, v.y.x, cnt, taken);
-            visit<T, PASS>(parent, ri, r, c + 3, v.y.y, cnt, taken);
-        }
-        for (; c < n; ++c) visit<T, PASS>(parent, ri, r, c, row[c], cnt, taken);
     }
     if constexpr (PASS != kRest) {
         for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
@@ -226,7 +275,8 @@ hipError_t launch_graph_features(DType dt, const void* D, int32_t n, int64_t ld,
     const int gi = (int)std::min<int64_t>(std::max<int64_t>((n + kThreads - 1) / kThreads, 1), 1024);
     hipLaunchKernelGGL(k_features_init, dim3(gi), dim3(kThreads), 0, st, parent, n > 1 ? n : 0, edges, roots);
     if (n > 1) {
-        const int gr = (int)std::min<int64_t>(n, 4096);
+        // at most kMaxSampleRows rows per workgroup
+        const int gr = (int)std::max<int64_t>(std::min<int64_t>(n, 4096), (n + kMaxSampleRows - 1) / kMaxSampleRows);
         auto pass = [&](auto tag, auto pass_c) {
             using T = decltype(tag);
             constexpr int PASS = decltype(pass_c)::value;
