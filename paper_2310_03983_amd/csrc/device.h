@@ -507,7 +507,8 @@ __device__ __forceinline__ void mp_tile(const typename S::T* __restrict__ A, int
 //   0. owners publish band r's rows and columns;
 //   1. pivot block (band x band): closed by min-plus squaring to a fixpoint
 //      (each pass doubles the hop reach; the closure equals the Eq. 1
-//      k-loop's), a few parallel passes instead of 32 barrier steps;
+//      k-loop's), or in close_block_wide by the k-loop itself, two steps per
+//      barrier over all lanes;
 //   2. panels: band rows x other columns <- P* (min,+) row panel and other
 //      rows x band columns <- column panel (min,+) P*, from the pre-update
 //      panels, then written back to R / Cc;
@@ -695,6 +696,16 @@ __device__ __forceinline__ void close_block(typename S::T* __restrict__ D, int64
 // the time.
 constexpr int kCloseWideThreads = 512;
 
+// Value of v in lane `lane` (0..63) of the calling lane's wave.
+__device__ __forceinline__ uint32_t group_value(uint32_t v, int lane)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(lane << 2, (int)v);
+}
+__device__ __forceinline__ float group_value(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(lane << 2, __float_as_int(v)));
+}
+
 template <class S>
 __device__ __forceinline__ void close_block_wide(typename S::T* __restrict__ D, int64_t ld, int s,
                                                  typename S::T* lds)
@@ -731,29 +742,44 @@ __device__ __forceinline__ void close_block_wide(typename S::T* __restrict__ D, 
 #pragma unroll
         for (int i = 0; i < 8; ++i) Cc[(ty + 16 * i) * kLdC + tx] = x[i][rd];
         __syncthreads();
-        // ---- 1. pivot block: squaring to a fixpoint (at most log2(32) + 1 passes change it)
-        for (int pass = 0; pass < 8; ++pass) {
-            T np[2];
+        // ---- 1. pivot block: the k-loop of Eq. 1 over the band's 32 steps,
+        //      two steps per barrier.  Lane t holds entries (t / 16,
+        //      2 (t % 16) + {0, 1}), so each 16-lane group holds one pivot row
+        //      and its lane k / 2 holds the row's columns k and k + 1.  Steps
+        //      k, k + 1 read rows k and k + 1 from R (their owners publish them
+        //      after the previous pair); every lane applies step k to row
+        //      k + 1 and to its own column k + 1 itself, then folds both
+        //      steps: min(x, x_k + r_k, x'_{k+1} + r'_{k+1}).  Row k does not
+        //      change in step k, nor column k.
+        {
+            const int pr = tid >> 4, pc = 2 * (tid & 15);
+            T pv[2] = {R[pr * kLdR + p0 + pc], R[pr * kLdR + p0 + pc + 1]};
 #pragma unroll
-            for (int a = 0; a < 2; ++a) np[a] = x[i0 + a][rd];
-#pragma unroll 4
-            for (int kk = 0; kk < kBand; kk += 2) {
-                const P pb = S::pair(R[kk * kLdR + p0 + tx], R[(kk + 1) * kLdR + p0 + tx]);
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-                    np[a] = S::fold(np[a], *reinterpret_cast<const P*>(&R[(ty + 16 * a) * kLdR + p0 + kk]), pb);
+            for (int k = 0; k < kBand; k += 2) {
+                const int src = (tid & 48) | (k >> 1);   // lane of the wave holding (pr, k), (pr, k + 1)
+                const T c0 = group_value(pv[0], src), c1 = group_value(pv[1], src);
+                const T* rk = R + k * kLdR + p0;
+                const T* rk1 = rk + kLdR;
+                const T a0 = rk[pc], a1 = rk[pc + 1];
+                const T e0 = S::relax(rk1[pc], rk1[k], a0), e1 = S::relax(rk1[pc + 1], rk1[k], a1);
+                const P ca = S::pair(c0, S::relax(c1, c0, rk[k + 1]));
+                pv[0] = S::fold(pv[0], ca, S::pair(a0, e0));
+                pv[1] = S::fold(pv[1], ca, S::pair(a1, e1));
+                if ((pr >> 1) == (k >> 1) + 1) {   // rows k + 2, k + 3: read by the next pair
+                    R[pr * kLdR + p0 + pc] = pv[0];
+                    R[pr * kLdR + p0 + pc + 1] = pv[1];
+                }
+                __syncthreads();
             }
-            const int changed = (np[0] < x[i0][rd]) | (np[1] < x[i0 + 1][rd]);
-            __syncthreads();
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                x[i0 + a][rd] = np[a];
-                R[(ty + 16 * a) * kLdR + p0 + tx] = np[a];
-            }
-            if (!__syncthreads_or(changed)) break;
+            R[pr * kLdR + p0 + pc] = pv[0];   // every row changes after it was published
+            R[pr * kLdR + p0 + pc + 1] = pv[1];
         }
+        __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 2; ++a) Cc[(ty + 16 * (i0 + a)) * kLdC + tx] = x[i0 + a][rd];
+        for (int a = 0; a < 2; ++a) {
+            x[i0 + a][rd] = R[(ty + 16 * a) * kLdR + p0 + tx];
+            Cc[(ty + 16 * (i0 + a)) * kLdC + tx] = x[i0 + a][rd];
+        }
         __syncthreads();
         // ---- 2. panels, from the closed pivot and the pre-update panels
         T nr[2][4], nc[8];
