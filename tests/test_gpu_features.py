@@ -74,6 +74,17 @@ def cases():
     F = np.where(rng.random((500, 500)) < 0.004, rng.uniform(0.1, 10, (500, 500)), np.inf).astype(np.float32)
     np.fill_diagonal(F, 0)
     out.append(("f32_500", F))
+    # below 1024 vertices (one workgroup, forest in LDS): two dense halves
+    # joined by one edge, then the same with the edge removed; n % 4 = 1
+    # and fp32
+    halves = np.full((701, 701), np.inf, np.float32)
+    halves[:350, :350] = np.where(rng.random((350, 350)) < 0.05, 1.5, np.inf)
+    halves[350:, 350:] = np.where(rng.random((351, 351)) < 0.05, 2.5, np.inf)
+    np.fill_diagonal(halves, 0)
+    bridged = halves.copy()
+    bridged[700, 3] = 4.0
+    out.append(("f32_halves701_bridged", bridged))
+    out.append(("f32_halves701", halves))
     return out
 
 
@@ -91,7 +102,7 @@ def test_features_strided_view(native, dev):
     """A matrix inside a wider buffer (row stride n + 3, rows not 16-byte
     aligned) gives the features of the matrix alone."""
     rng = np.random.default_rng(78)
-    for n in (1027, 2050):
+    for n in (301, 999, 1027, 2050):
         W = np.where(rng.random((n, n)) < 0.003, rng.integers(1, 100, (n, n)), INF).astype(np.int32)
         np.fill_diagonal(W, 0)
         buf = torch.zeros((n, n + 3), dtype=torch.int32, device=dev)   # zeros outside: would count as edges
