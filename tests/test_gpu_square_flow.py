@@ -3,9 +3,9 @@
 waiting on the previous pass's counter, convergence detected on the
 device): int32 bit-exact against the oracle's Eq. 1 loop, fp32 within 1e-5
 of the fp64 oracle, on graphs that need the most passes (a path through
-every vertex), disconnected graphs, strided views, ragged sizes, and
-back-to-back calls (the counters are reset per launch); the reported pass
-count stays within ceil(log2(n - 1))."""
+every vertex), disconnected graphs, strided views, ragged sizes on both
+tile sizes, and back-to-back calls (the counters are reset per launch);
+the reported pass count stays within ceil(log2(n - 1))."""
 import os
 
 import numpy as np
@@ -48,7 +48,7 @@ def path_i32(rng, n):
 
 
 CASES = [("rand", 3, 0.5), ("rand", 4, 0.0), ("rand", 63, 0.2), ("rand", 64, 0.05), ("rand", 65, 0.05),
-         ("rand", 200, 0.02), ("rand", 256, 0.1), ("rand", 257, 0.003), ("path", 300, 0), ("rand", 511, 0.02),
+         ("rand", 200, 0.02), ("rand", 256, 0.1), ("rand", 257, 0.003), ("path", 300, 0), ("rand", 400, 0.02), ("path", 450, 0), ("rand", 511, 0.02),
          ("rand", 512, 0.3), ("path", 512, 0), ("rand", 700, 0.01),
          ("path", 1024, 0), ("rand", 1024, 0.002), ("rand", 1500, 0.004), ("rand", 2048, 0.01), ("path", 2048, 0)]
 
