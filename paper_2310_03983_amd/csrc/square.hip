@@ -35,7 +35,6 @@ namespace apsp {
 namespace {
 
 constexpr int kSqThreads = 256;
-constexpr int kSqKT = 32;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
 // Words of the synchronisation block (uint32 indices): the ticket counter,
@@ -56,6 +55,9 @@ __global__ __launch_bounds__(kSqThreads) void k_square_flow(typename S::T* D, in
 {
     using P = typename S::P;
     constexpr int TM = TILE / 16;   // 16 x 16 lanes, TM x TM entries each
+    // reduction steps per staged slice: the small tiles' few slices are
+    // latency-bound, so they take longer slices
+    constexpr int kSqKT = TILE == 32 ? 64 : 32;
     __shared__ P As[2][kSqKT / S::KPACK][TILE + 2];
     __shared__ P Bs[2][kSqKT / S::KPACK][TILE + 2];
     __shared__ int s_ticket;
