@@ -178,9 +178,13 @@ __global__ __launch_bounds__(kThreads) void k_graph_edges(const T* __restrict__ 
         const T* row = D + (int64_t)r * ld;
         int32_t ri = r;
         if constexpr (PASS != kSample) ri = find_root(parent, r);
-        // kSample: this wave's slots of the row (nothing is recorded past kMaxSampleRows)
-        int32_t* slots = s_slots + (rows * kWaves + (threadIdx.x >> 6)) * kWaveSample;
-        int taken = PASS == kSample && rows < kMaxSampleRows ? 0 : kWaveSample;
+        // kSample: this wave's slots of the row; past kMaxSampleRows rows
+        // nothing is recorded (taken starts full)
+        const bool record = PASS == kSample && rows < kMaxSampleRows;
+        int32_t* slots = nullptr;
+        if constexpr (PASS == kSample)
+            slots = s_slots + ((record ? rows : 0) * kWaves + (threadIdx.x >> 6)) * kWaveSample;
+        int taken = record ? 0 : kWaveSample;
         auto visit = [&](uint32_t mask, int32_t col0, int32_t stride) {
             if constexpr (PASS != kRest) cnt += __popc(mask);
             if constexpr (PASS == kSample) sample_marked(slots, mask, col0, stride, taken);
